@@ -1,0 +1,225 @@
+/*
+ * dwf.h -- C ABI of libdwf: conjugate gradient on the 4D even-odd
+ * preconditioned 5D domain-wall fermion operator on one MI355X (gfx950).
+ *
+ * The operator is the general domain-wall operator of Eq. (1)/(5) of Chiu,
+ * Hsieh, Mao, Ogawa, "GPU-Based Conjugate Gradient Solver for Lattice QCD
+ * with Domain-Wall Fermions" (Lattice 2010):
+ *
+ *     D(mq) = D_w (omega + sigma L) + (1 - L),
+ *
+ * with the Wilson operator D_w of Eq. (2) (d = 4, 0 < m0 < 2), the chiral
+ * fifth-dimension hopping L = P_+ L_+ + P_- L_- of Eqs. (3)-(4) and arbitrary
+ * per-slice weights sigma_s, omega_s (Shamir: sigma = 0, omega = 1; Borici:
+ * sigma = omega = 1; optimal DWF: sigma = omega).  Solves go through the
+ * even-odd factorisation of Eq. (10) and the Schur complement
+ * C = 1 - M5 D_w^OE M5 D_w^EO of Eq. (11), with CG (Algorithm 1) on C C^dag,
+ * mixed-precision defect correction (Algorithm 2) and reliable updates with
+ * automatic fallback to defect correction (Sec. 2.3).
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - chiral gamma basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]],
+ *     gamma_4 = [[0, 1], [1, 0]], gamma_5 = diag(1, 1, -1, -1);
+ *     mu = 0, 1, 2, 3 is x, y, z, t;
+ *   - periodic boundaries (optionally antiperiodic in t, dwf_opts);
+ *   - D_w^EO maps odd 4D sites to even ones; C acts on odd sites;
+ *     parity of (x, y, z, t) is (x + y + z + t) mod 2, even = 0.
+ *
+ * Host layouts (canonical, Sec. 3.1 Eq. (12)):
+ *   gauge  : double [Lt][Lz][Ly][Lx][mu][a][b][re, im]; U_mu(x) is the
+ *            SU(3) link from x to x + mu^.
+ *   spinor : double [Lt][Lz][Ly][Lx][s][24]; the 24 reals of a site are
+ *            c = 2 * (3 * spin + colour) + reim.  With nrhs > 1 the
+ *            right-hand sides follow each other (stride = one spinor).
+ *
+ * Errors: every function returns DWF_OK (0) or a negative DWF_E* code and
+ * never throws; dwf_last_error() gives a message for the calling thread.
+ * Ownership: the caller owns all buffers it passes; the library reads or
+ * writes them only during the call (dwf_submit copies b before returning,
+ * dwf_poll writes x only when it returns a final status).  A context owns
+ * all device memory it allocates; dwf_destroy frees it.
+ */
+#ifndef DWF_H
+#define DWF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DWF_OK 0
+#define DWF_PENDING 1
+#define DWF_EINVAL (-1)
+#define DWF_ENOMEM (-2)
+#define DWF_EDEVICE (-3)
+#define DWF_ENOCONV (-4)
+#define DWF_EBUSY (-5)
+#define DWF_ENOTFOUND (-6)
+
+/* operators for dwf_apply (all in the host spinor layout, full 5D lattice) */
+#define DWF_OP_DW 0      /* D_w on every slice, Eq. (2)                                */
+#define DWF_OP_HOP_EO 1  /* D_w^EO: hopping term, odd -> even (Eq. (14)); odd out = 0 */
+#define DWF_OP_HOP_OE 2  /* D_w^OE: even -> odd; even out = 0                          */
+#define DWF_OP_M5 3      /* M5 of Eq. (8), per 4D site                                 */
+#define DWF_OP_M5T 4     /* M5^T                                                       */
+#define DWF_OP_C 5       /* C = 1 - M5 D^OE M5 D^EO on odd sites (Eq. (11)); even out = 0 */
+#define DWF_OP_CDAG 6    /* C^dag = g5 (1 - D^OE M5^T D^EO M5^T) g5                   */
+#define DWF_OP_CCDAG 7   /* C C^dag                                                    */
+#define DWF_OP_D 8       /* the 5D operator D of Eq. (5)                               */
+#define DWF_OP_DDAG 9    /* D^dag                                                      */
+
+/* arithmetic / storage precision */
+#define DWF_PREC_FP64 0
+#define DWF_PREC_FP32 1
+#define DWF_PREC_FP16 2  /* binary16 storage with one FP32 scale per 5D site, FP32 arithmetic */
+
+typedef struct dwf_ctx dwf_ctx;
+
+typedef struct dwf_opts {
+    int antiperiodic_t;      /* 0: periodic in t (default); 1: antiperiodic               */
+    int device;              /* HIP device ordinal (default 0)                            */
+    int sites_per_block;     /* 4D sites per workgroup in the stencil; 0 = automatic      */
+    int reserved0;
+    size_t hbm_budget_bytes; /* serving admission budget; 0 = 80% of free device memory   */
+} dwf_opts;
+
+typedef struct dwf_solve_params {
+    double tol;              /* target ||b - D x|| / ||b|| (default 1e-10)               */
+    int inner_prec;          /* DWF_PREC_FP32 (default), DWF_PREC_FP16 or DWF_PREC_FP64   */
+    int reliable;            /* 1: reliable updates, falling back to defect correction
+                                when they stall (default); 0: defect correction only     */
+    double eps_inner;        /* inner relative tolerance; 0 = per-precision default       */
+    int maxiter;             /* cap on inner iterations per right-hand side (default 50000) */
+    int check_every;         /* inner iterations between host checks; 0 = adaptive        */
+    int use_graph;           /* 1: capture inner iterations in a hipGraph (default)       */
+    int link_compress;       /* -1 auto (12-real for FP16), 0: 18-real, 1: 12-real links  */
+    int use_guess;           /* 1: x holds an initial guess on entry; 0: start from zero  */
+    int debug_stall_after;   /* test hook: >0 declares reliable updates stalled after this
+                                many restarts, forcing the defect-correction fallback     */
+} dwf_solve_params;
+
+typedef struct dwf_solve_stats {
+    int status;              /* DWF_OK or DWF_ENOCONV                                     */
+    int iters;               /* inner CG iterations                                       */
+    int restarts;            /* outer high-precision residual recomputations              */
+    int reliable_updates;    /* restarts taken in reliable-update mode (p kept)           */
+    int fallback;            /* 1 if the solve switched to defect correction              */
+    int reserved0;
+    double true_residual;    /* ||b - D x|| / ||b||, FP64 full operator on the GPU        */
+    double schur_residual;   /* ||b'' - C y|| / ||b''|| of the final iterate              */
+    double seconds;          /* wall time of the solve on the device stream               */
+    double gflops;           /* paper-convention flops / seconds (see DESIGN)             */
+    double hbm_gbytes;       /* algorithmic HBM bytes moved / 1e9                         */
+} dwf_solve_stats;
+
+/* Fill defaults. */
+void dwf_default_opts(dwf_opts *opts);
+void dwf_default_params(dwf_solve_params *params);
+
+/*
+ * dwf_create -- build one operator: resident gauge field and fifth-dimension
+ * tables (Eqs. (1)-(9)).
+ *   gauge  : host pointer, FP64, layout above (copied to the device).
+ *   dims   : Lx, Ly, Lz, Lt, each even and >= 2.
+ *   Ns     : 1 <= Ns <= 32.   m0 in (0, 2).   mq: quark mass (kappa = mq / (2 m0)).
+ *   sigma, omega : host arrays of Ns doubles, omega_s > 0.
+ *   opts   : NULL for defaults.
+ * Errors: DWF_EINVAL for bad sizes or parameters, or when (1 + cL) or X of
+ * Eq. (7) is singular; DWF_ENOMEM; DWF_EDEVICE.
+ */
+int dwf_create(dwf_ctx **out, const double *gauge, const int dims[4], int Ns,
+               double m0, double mq, const double *sigma, const double *omega,
+               const dwf_opts *opts);
+
+/* Release a context and all its device memory (NULL is ignored). */
+void dwf_destroy(dwf_ctx *ctx);
+
+/*
+ * dwf_apply -- out = op(in) for nrhs spinors in the host layout, in
+ * precision prec (inputs are rounded to prec, outputs returned in FP64).
+ * in, out: host pointers of nrhs * V4 * Ns * 24 doubles.
+ */
+int dwf_apply(dwf_ctx *ctx, int op, int prec, const double *in, double *out, int nrhs);
+
+/* Same, with device pointers (host layout, FP64) on a HIP stream (NULL =
+ * the context's stream); returns after the work is enqueued and finished. */
+int dwf_apply_dev(dwf_ctx *ctx, int op, int prec, const double *in_dev, double *out_dev,
+                  int nrhs, void *hip_stream);
+
+/*
+ * dwf_solve -- solve D x = b (Eq. (5)) for nrhs right-hand sides.
+ *   b, x  : host pointers, nrhs spinors in the host layout.  x is read as
+ *           the initial guess when params->use_guess, and holds the
+ *           solution on return (the best iterate on DWF_ENOCONV).
+ *   params: NULL for defaults.   stats: NULL or nrhs entries.
+ * With nrhs > 1 the right-hand sides are solved together through the
+ * multi-RHS stencil (each gauge link is read once for all of them).
+ * Returns DWF_OK when every right-hand side reached params->tol, else
+ * DWF_ENOCONV.
+ */
+int dwf_solve(dwf_ctx *ctx, const double *b, double *x, int nrhs,
+              const dwf_solve_params *params, dwf_solve_stats *stats);
+
+/* Same, with device pointers (FP64, host layout) on a HIP stream. */
+int dwf_solve_dev(dwf_ctx *ctx, const double *b_dev, double *x_dev, int nrhs,
+                  const dwf_solve_params *params, dwf_solve_stats *stats, void *hip_stream);
+
+/*
+ * dwf_submit -- enqueue one solve request on the context's device server
+ * (continuous batching: requests on the same gauge field and fifth-dimension
+ * weights are solved together in the multi-RHS kernels, with their own mq;
+ * admission is limited by the HBM budget of dwf_opts).  b (host, one spinor)
+ * is copied before the call returns.  *ticket identifies the request.
+ */
+int dwf_submit(dwf_ctx *ctx, const double *b, const dwf_solve_params *params, uint64_t *ticket);
+
+/* Same, with the quark mass of this request (the context's mq otherwise). */
+int dwf_submit_mass(dwf_ctx *ctx, const double *b, double mq, const dwf_solve_params *params,
+                    uint64_t *ticket);
+
+/*
+ * dwf_poll -- wait up to timeout_us (0: do not wait, <0: forever) for a
+ * request.  Returns DWF_PENDING while it runs; otherwise its final status
+ * (DWF_OK / DWF_ENOCONV / error), writes x (host, one spinor) and *stats
+ * (may be NULL) and forgets the ticket.  DWF_ENOTFOUND for unknown tickets.
+ */
+int dwf_poll(uint64_t ticket, double *x, dwf_solve_stats *stats, int timeout_us);
+
+/* Server statistics since the last reset: latencies in seconds. */
+typedef struct dwf_server_stats {
+    int64_t completed;
+    int64_t admitted;
+    int64_t peak_batch;
+    int64_t waits_for_memory;
+    double p50_latency;
+    double p99_latency;
+    double busy_seconds;
+} dwf_server_stats;
+int dwf_server_stats_get(dwf_server_stats *out, int reset);
+
+/*
+ * dwf_time_kernels -- profiling aid: average device time (milliseconds) of
+ * each kernel of one inner CG iteration, in the order E, A, B, C, D (see
+ * DESIGN), over `launches` back-to-back launches on the context's stream
+ * bracketed by HIP events, and the algorithmic HBM bytes one launch must move
+ * (every operand read or written once).  Uses the workspace left by the last
+ * dwf_solve/dwf_solve_dev with the same params and nrhs (DWF_EINVAL if there
+ * is none); it overwrites that workspace's low-precision vectors.
+ */
+int dwf_time_kernels(dwf_ctx *ctx, const dwf_solve_params *params, int nrhs, int launches,
+                     double ms[5], double bytes[5]);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *dwf_last_error(void);
+
+/* Library version string. */
+const char *dwf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWF_H */

@@ -1,0 +1,267 @@
+"""ctypes binding of include/dwf.h (same names, argument marshalling only).
+
+Host arrays are numpy float64 in the canonical layouts of dwf.h; device
+arrays are torch CUDA (HIP) float64 tensors whose data pointers are passed
+straight through together with the current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libdwf.so")
+
+DWF_OK, DWF_PENDING = 0, 1
+DWF_EINVAL, DWF_ENOMEM, DWF_EDEVICE, DWF_ENOCONV, DWF_EBUSY, DWF_ENOTFOUND = -1, -2, -3, -4, -5, -6
+(OP_DW, OP_HOP_EO, OP_HOP_OE, OP_M5, OP_M5T, OP_C, OP_CDAG, OP_CCDAG, OP_D, OP_DDAG) = range(10)
+PREC_FP64, PREC_FP32, PREC_FP16 = 0, 1, 2
+
+# every function declared in include/dwf.h
+EXPORTED = [
+    "dwf_default_opts", "dwf_default_params", "dwf_create", "dwf_destroy", "dwf_apply", "dwf_apply_dev",
+    "dwf_solve", "dwf_solve_dev", "dwf_submit", "dwf_submit_mass", "dwf_poll", "dwf_server_stats_get",
+    "dwf_time_kernels", "dwf_last_error", "dwf_version",
+]
+
+
+class DwfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdwf error {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("antiperiodic_t", ctypes.c_int), ("device", ctypes.c_int), ("sites_per_block", ctypes.c_int),
+                ("reserved0", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("inner_prec", ctypes.c_int), ("reliable", ctypes.c_int),
+                ("eps_inner", ctypes.c_double), ("maxiter", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("link_compress", ctypes.c_int), ("use_guess", ctypes.c_int),
+                ("debug_stall_after", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("reliable_updates", ctypes.c_int), ("fallback", ctypes.c_int), ("reserved0", ctypes.c_int),
+                ("true_residual", ctypes.c_double), ("schur_residual", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("gflops", ctypes.c_double), ("hbm_gbytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("admitted", ctypes.c_int64), ("peak_batch", ctypes.c_int64),
+                ("waits_for_memory", ctypes.c_int64), ("p50_latency", ctypes.c_double),
+                ("p99_latency", ctypes.c_double), ("busy_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def lib_path():
+    return _LIB_PATH
+
+
+def lib():
+    """Load libdwf.so; raises if it is not built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run paper_1101_0423_amd/build.py "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp = ctypes.c_void_p
+    L.dwf_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.dwf_default_params.argtypes = [ctypes.POINTER(SolveParams)]
+    L.dwf_create.argtypes = [ctypes.POINTER(vp), _dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_double,
+                             ctypes.c_double, _dp, _dp, ctypes.POINTER(Opts)]
+    L.dwf_destroy.argtypes = [vp]
+    L.dwf_destroy.restype = None
+    L.dwf_apply.argtypes = [vp, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int]
+    L.dwf_apply_dev.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+    L.dwf_solve.argtypes = [vp, _dp, _dp, ctypes.c_int, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats)]
+    L.dwf_solve_dev.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats),
+                                vp]
+    L.dwf_submit.argtypes = [vp, _dp, ctypes.POINTER(SolveParams), ctypes.POINTER(ctypes.c_uint64)]
+    L.dwf_submit_mass.argtypes = [vp, _dp, ctypes.c_double, ctypes.POINTER(SolveParams),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+    L.dwf_poll.argtypes = [ctypes.c_uint64, _dp, ctypes.POINTER(SolveStats), ctypes.c_int]
+    L.dwf_server_stats_get.argtypes = [ctypes.POINTER(ServerStats), ctypes.c_int]
+    L.dwf_time_kernels.argtypes = [vp, ctypes.POINTER(SolveParams), ctypes.c_int, ctypes.c_int, _dp, _dp]
+    L.dwf_last_error.restype = ctypes.c_char_p
+    L.dwf_version.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+def last_error():
+    return lib().dwf_last_error().decode()
+
+
+def _check(rc, ok=(DWF_OK,)):
+    if rc not in ok:
+        raise DwfError(rc, last_error())
+    return rc
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def default_params(**kw):
+    p = SolveParams()
+    lib().dwf_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+class Context:
+    """One operator: resident gauge field and fifth-dimension tables (dwf_create)."""
+
+    def __init__(self, gauge, dims, ns, m0, mq, sigma, omega, antiperiodic_t=False, device=0,
+                 sites_per_block=0, hbm_budget_bytes=0):
+        L = lib()
+        self._h = ctypes.c_void_p()
+        o = Opts()
+        L.dwf_default_opts(ctypes.byref(o))
+        o.antiperiodic_t = int(antiperiodic_t)
+        o.device = device
+        o.sites_per_block = sites_per_block
+        o.hbm_budget_bytes = hbm_budget_bytes
+        self.gauge = _f64(gauge)
+        self.dims = tuple(int(d) for d in dims)
+        self.ns, self.m0, self.mq = int(ns), float(m0), float(mq)
+        self.sigma, self.omega = _f64(sigma), _f64(omega)
+        d = (ctypes.c_int * 4)(*self.dims)
+        _check(L.dwf_create(ctypes.byref(self._h), _ptr(self.gauge), d, self.ns, self.m0, self.mq,
+                            _ptr(self.sigma), _ptr(self.omega), ctypes.byref(o)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def spinor_shape(self, nrhs=None):
+        lx, ly, lz, lt = self.dims
+        s = (lt, lz, ly, lx, self.ns, 24)
+        return s if nrhs is None else (nrhs,) + s
+
+    def close(self):
+        if self._h:
+            lib().dwf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- operators -------------------------------------------------------
+    def apply(self, op, psi, prec=PREC_FP64):
+        """out = op(psi) for host arrays [nrhs?][Lt][Lz][Ly][Lx][Ns][24]."""
+        psi = _f64(psi)
+        nrhs = 1 if psi.ndim == 6 else psi.shape[0]
+        out = np.empty_like(psi)
+        _check(lib().dwf_apply(self._h, op, prec, _ptr(psi), _ptr(out), nrhs))
+        return out
+
+    def apply_dev(self, op, psi, out, prec=PREC_FP64, nrhs=1, stream=None):
+        """Device tensors (torch float64, contiguous, host layout)."""
+        _check(lib().dwf_apply_dev(self._h, op, prec, ctypes.c_void_p(psi.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), nrhs, _stream_ptr(stream)))
+        return out
+
+    # -- solves ----------------------------------------------------------
+    def solve(self, b, x0=None, params=None, **kw):
+        """Solve D x = b for host arrays; returns (x, [stats dict per rhs], status)."""
+        b = _f64(b)
+        nrhs = 1 if b.ndim == 6 else b.shape[0]
+        p = params if params is not None else default_params(**kw)
+        if x0 is not None:
+            x = _f64(x0).copy()
+            p.use_guess = 1
+        else:
+            x = np.zeros_like(b)
+        st = (SolveStats * nrhs)()
+        rc = _check(lib().dwf_solve(self._h, _ptr(b), _ptr(x), nrhs, ctypes.byref(p), st),
+                    ok=(DWF_OK, DWF_ENOCONV))
+        return x, [s.as_dict() for s in st], rc
+
+    def solve_dev(self, b, x, nrhs=1, params=None, stream=None, **kw):
+        p = params if params is not None else default_params(**kw)
+        st = (SolveStats * nrhs)()
+        rc = _check(lib().dwf_solve_dev(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                        nrhs, ctypes.byref(p), st, _stream_ptr(stream)),
+                    ok=(DWF_OK, DWF_ENOCONV))
+        return [s.as_dict() for s in st], rc
+
+    def time_kernels(self, params=None, nrhs=1, launches=20, **kw):
+        """Average ms and algorithmic bytes of the inner kernels E, A, B, C, D."""
+        p = params if params is not None else default_params(**kw)
+        ms = np.zeros(5)
+        by = np.zeros(5)
+        _check(lib().dwf_time_kernels(self._h, ctypes.byref(p), nrhs, launches, _ptr(ms), _ptr(by)))
+        return dict(zip("EABCD", ms)), dict(zip("EABCD", by))
+
+    # -- serving ---------------------------------------------------------
+    def submit(self, b, mq=None, params=None, **kw):
+        b = _f64(b)
+        p = params if params is not None else default_params(**kw)
+        t = ctypes.c_uint64()
+        if mq is None:
+            _check(lib().dwf_submit(self._h, _ptr(b), ctypes.byref(p), ctypes.byref(t)))
+        else:
+            _check(lib().dwf_submit_mass(self._h, _ptr(b), float(mq), ctypes.byref(p), ctypes.byref(t)))
+        return t.value
+
+
+def poll(ticket, shape, timeout_us=0):
+    """Returns (status, x or None, stats dict or None)."""
+    x = np.empty(shape, dtype=np.float64)
+    st = SolveStats()
+    rc = lib().dwf_poll(ctypes.c_uint64(ticket), _ptr(x), ctypes.byref(st), int(timeout_us))
+    if rc == DWF_PENDING:
+        return rc, None, None
+    if rc not in (DWF_OK, DWF_ENOCONV):
+        raise DwfError(rc, last_error())
+    return rc, x, st.as_dict()
+
+
+def server_stats(reset=False):
+    s = ServerStats()
+    _check(lib().dwf_server_stats_get(ctypes.byref(s), int(reset)))
+    return s.as_dict()

@@ -1,0 +1,453 @@
+// api.hip -- the C ABI of libdwf (include/dwf.h): contexts, the resident
+// gauge field, the fifth-dimension tables of Eqs. (7)-(9), error reporting,
+// and the thin host-pointer wrappers around the device-pointer entry points.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+
+#include "dwf_ctx.h"
+
+namespace dwf {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int DevBuf::alloc(size_t n) {
+    release();
+    if (n == 0) return DWF_OK;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? DWF_ENOMEM : DWF_EDEVICE,
+                    std::string("hipMalloc(") + std::to_string(n) + "): " + hipGetErrorString(e));
+    }
+    bytes = n;
+    return DWF_OK;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+int HalfField::alloc(int prec_, long V5h, int nrhs_) {
+    prec = prec_;
+    nrhs = nrhs_;
+    // pad every component block; the extra 64 elements stagger the blocks
+    // over the HBM channels
+    stride = ((V5h + 255) / 256) * 256 + 64;
+    int nblk = prec == DWF_PREC_FP64 ? 12 : prec == DWF_PREC_FP32 ? 6 : 3;
+    rstride = stride * nblk;
+    int rc = data.alloc((size_t)rstride * nrhs * 16);
+    if (rc) return rc;
+    if (prec == DWF_PREC_FP16) {
+        rc = nrm.alloc((size_t)stride * nrhs * sizeof(float));
+        if (rc) return rc;
+    }
+    return DWF_OK;
+}
+
+int Workspace::alloc(const std::vector<int>& precs, long V5h, int nrhs_) {
+    nrhs = nrhs_;
+    fields.clear();
+    for (int pr : precs) {
+        fields.emplace_back(new HalfField);
+        int rc = fields.back()->alloc(pr, V5h, nrhs_);
+        if (rc) return rc;
+    }
+    return DWF_OK;
+}
+
+int Workspace::alloc_state(int n) {
+    // 6 double arrays + 4 int arrays of length n
+    size_t nd = 6 * (size_t)n, ni = 4 * (size_t)n;
+    int rc = state.alloc(nd * sizeof(double) + ni * sizeof(int));
+    if (rc) return rc;
+    double* d = state.as<double>();
+    int* i = (int*)(d + nd);
+    st.rr = d;
+    st.uu = d + n;
+    st.alpha = d + 2 * n;
+    st.beta = d + 3 * n;
+    st.rr_target = d + 4 * n;
+    st.aux = d + 5 * n;
+    st.live = i;
+    st.iters = i + n;
+    st.status = i + 2 * n;
+    st.maxiter = i + 3 * n;
+    hipError_t e = hipMemset(state.p, 0, state.bytes);
+    if (e != hipSuccess) return fail(DWF_EDEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
+    return DWF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fifth-dimension tables, Eqs. (3)-(4), (7)-(9)
+// ---------------------------------------------------------------------------
+
+// Solve (diag(a) + diag(b) L) w = z with L = L_+ (ch = 0) or L_- (ch = 1),
+// L_+ w_s = w_{s-1} (s >= 1), L_+ w_0 = -kappa w_{Ns-1}, L_- = L_+^T.  The
+// cyclic bidiagonal system is solved in O(Ns): every w_s is affine in w_0,
+// and the corner equation fixes w_0.  Returns false if singular.
+static bool cyc_solve(int N, const double* a, const double* b, double kappa, int ch, const double* z, double* w) {
+    std::vector<double> A(N), B(N), Z(N), al(N), be(N);
+    for (int s = 0; s < N; ++s) {
+        int k = ch ? N - 1 - s : s;  // L_- is L_+ with s reversed
+        A[s] = a[k];
+        B[s] = b[k];
+        Z[s] = z[k];
+    }
+    al[0] = 0;
+    be[0] = 1;
+    for (int s = 1; s < N; ++s) {
+        if (A[s] == 0) return false;
+        al[s] = (Z[s] - B[s] * al[s - 1]) / A[s];
+        be[s] = -B[s] * be[s - 1] / A[s];
+    }
+    double den = A[0] - kappa * B[0] * be[N - 1];
+    double scale = fabs(A[0]) + fabs(kappa * B[0] * be[N - 1]);
+    if (!(fabs(den) > 1e-13 * scale)) return false;
+    double w0 = (Z[0] + kappa * B[0] * al[N - 1]) / den;
+    for (int s = 0; s < N; ++s) {
+        int k = ch ? N - 1 - s : s;
+        w[k] = al[s] + be[s] * w0;
+    }
+    return true;
+}
+
+bool build_tables(int N, double m0, double mq, const double* sigma, const double* omega, std::vector<double>& out,
+                  std::string& why) {
+    const double kappa = mq / (2.0 * m0);
+    const size_t blk = (size_t)2 * N * N;
+    out.assign(blk * TB_COUNT, 0.0);
+    std::vector<double> a(N), b(N), one(N, 1.0), c(N), col(N), e(N), sw(N);
+    for (int s = 0; s < N; ++s) {
+        c[s] = sigma[s] / omega[s];
+        sw[s] = sqrt(omega[s]);
+    }
+    for (int ch = 0; ch < 2; ++ch) {
+        auto T = [&](int t, int s, int u) -> double& { return out[t * blk + (size_t)ch * N * N + (size_t)s * N + u]; };
+        // L of this chirality
+        std::vector<double> L((size_t)N * N, 0.0);
+        for (int s = 1; s < N; ++s) L[(size_t)s * N + s - 1] = 1.0;
+        L[N - 1] += -kappa;
+        if (ch) {
+            std::vector<double> Lt((size_t)N * N);
+            for (int s = 0; s < N; ++s)
+                for (int u = 0; u < N; ++u) Lt[(size_t)s * N + u] = L[(size_t)u * N + s];
+            L.swap(Lt);
+        }
+        // (1 + cL) must be invertible (Eq. (7))
+        for (int s = 0; s < N; ++s) e[s] = s == 0;
+        if (!cyc_solve(N, one.data(), c.data(), kappa, ch, e.data(), col.data())) {
+            why = "1 + cL is singular for these weights and mass";
+            return false;
+        }
+        // X = (d - m0) omega (1 + cL) + (1 - L) = a + b L, Y = omega + sigma L
+        for (int s = 0; s < N; ++s) {
+            a[s] = (4.0 - m0) * omega[s] + 1.0;
+            b[s] = (4.0 - m0) * sigma[s] - 1.0;
+        }
+        std::vector<double> Xi((size_t)N * N), Yi((size_t)N * N);
+        for (int u = 0; u < N; ++u) {
+            for (int s = 0; s < N; ++s) e[s] = s == u;
+            if (!cyc_solve(N, a.data(), b.data(), kappa, ch, e.data(), col.data())) {
+                why = "X of Eq. (7) is singular for these weights and mass";
+                return false;
+            }
+            for (int s = 0; s < N; ++s) Xi[(size_t)s * N + u] = col[s];
+            if (!cyc_solve(N, omega, sigma, kappa, ch, e.data(), col.data())) {
+                why = "Y of Eq. (7) is singular for these weights and mass";
+                return false;
+            }
+            for (int s = 0; s < N; ++s) Yi[(size_t)s * N + u] = col[s];
+        }
+        for (int s = 0; s < N; ++s)
+            for (int u = 0; u < N; ++u) {
+                double id = s == u;
+                double Lsu = L[(size_t)s * N + u];
+                T(TB_X, s, u) = a[s] * id + b[s] * Lsu;
+                T(TB_Y, s, u) = omega[s] * id + sigma[s] * Lsu;
+                T(TB_1MLT, u, s) = id - Lsu;
+                T(TB_G5, s, u) = ch ? -id : id;
+            }
+        // M5 = sqrt(w)^-1 Y X^-1 sqrt(w)   (Eq. (8))
+        for (int s = 0; s < N; ++s)
+            for (int u = 0; u < N; ++u) {
+                double acc = 0;
+                for (int k = 0; k < N; ++k) acc += T(TB_Y, s, k) * Xi[(size_t)k * N + u];
+                T(TB_M5, s, u) = acc * sw[u] / sw[s];
+            }
+        for (int s = 0; s < N; ++s)
+            for (int u = 0; u < N; ++u) {
+                const double m = T(TB_M5, s, u);
+                T(TB_M5T, u, s) = m;
+                T(TB_M5TG5, u, s) = ch ? -m : m;
+                T(TB_S1, s, u) = m / sw[u];                       // S1 = M5 sqrt(w)^-1
+                T(TB_S2, s, u) = Yi[(size_t)s * N + u] * sw[u];   // S2 = Y^-1 sqrt(w)
+                T(TB_S2INV, s, u) = T(TB_Y, s, u) / sw[s];        // S2^-1 = sqrt(w)^-1 Y
+                T(TB_YTG5, u, s) = ch ? -T(TB_Y, s, u) : T(TB_Y, s, u);
+            }
+    }
+    for (double v : out)
+        if (!std::isfinite(v)) {
+            why = "non-finite fifth-dimension table";
+            return false;
+        }
+    return true;
+}
+
+}  // namespace dwf
+
+using namespace dwf;
+
+dwf::Geom dwf_ctx::geom(int out_parity, bool fp64) const {
+    Geom g;
+    g.Lx = dims[0];
+    g.Ly = dims[1];
+    g.Lz = dims[2];
+    g.Lt = dims[3];
+    g.Lxh = dims[0] / 2;
+    g.Ns = Ns;
+    g.G = fp64 ? G64 : G32;
+    g.V4h = (int)V4h;
+    g.out_parity = out_parity;
+    g.antiper = opts.antiperiodic_t ? 1 : 0;
+    g.nblocks = (int)((V4h + g.G - 1) / g.G);
+    g.xcd = 1;
+    return g;
+}
+
+const TableSet* dwf_ctx::table_set(double mq_val, int* rc) {
+    auto it = tables.find(mq_val);
+    if (it != tables.end()) {
+        *rc = DWF_OK;
+        return it->second.get();
+    }
+    std::unique_ptr<TableSet> ts(new TableSet);
+    ts->mq = mq_val;
+    std::string why;
+    if (!build_tables(Ns, m0, mq_val, sigma.data(), omega.data(), ts->host, why)) {
+        *rc = fail(DWF_EINVAL, why);
+        return nullptr;
+    }
+    size_t n = ts->host.size();
+    std::vector<float> h32(n);
+    for (size_t i = 0; i < n; ++i) h32[i] = (float)ts->host[i];
+    if ((*rc = ts->d64.alloc(n * sizeof(double)))) return nullptr;
+    if ((*rc = ts->d32.alloc(n * sizeof(float)))) return nullptr;
+    hipError_t e = hipMemcpy(ts->d64.p, ts->host.data(), n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ts->d32.p, h32.data(), n * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        *rc = fail(DWF_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
+        return nullptr;
+    }
+    TableSet* raw = ts.get();
+    tables[mq_val] = std::move(ts);
+    *rc = DWF_OK;
+    return raw;
+}
+
+int dwf_ctx::ensure_partials(size_t n) {
+    size_t need = n * sizeof(double);
+    if (partials_bytes >= need) return DWF_OK;
+    int rc = partials.alloc(need);
+    if (rc) return rc;
+    partials_bytes = need;
+    return DWF_OK;
+}
+
+extern "C" {
+
+void dwf_default_opts(dwf_opts* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+}
+
+void dwf_default_params(dwf_solve_params* p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->tol = 1e-10;
+    p->inner_prec = DWF_PREC_FP32;
+    p->reliable = 1;
+    p->eps_inner = 0;
+    p->maxiter = 50000;
+    p->check_every = 0;
+    p->use_graph = 1;
+    p->link_compress = -1;
+    p->use_guess = 0;
+    p->debug_stall_after = 0;
+}
+
+const char* dwf_last_error(void) { return g_err.c_str(); }
+
+const char* dwf_version(void) { return "libdwf 0.1 (gfx950)"; }
+
+int dwf_create(dwf_ctx** out, const double* gauge, const int dims[4], int Ns, double m0, double mq,
+               const double* sigma, const double* omega, const dwf_opts* opts) {
+    g_err.clear();
+    if (!out) return fail(DWF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!gauge || !dims || !sigma || !omega) return fail(DWF_EINVAL, "NULL gauge, dims, sigma or omega");
+    for (int i = 0; i < 4; ++i)
+        if (dims[i] < 2 || dims[i] % 2) return fail(DWF_EINVAL, "every lattice extent must be even and >= 2");
+    if (Ns < 1 || Ns > 32) return fail(DWF_EINVAL, "Ns must be in [1, 32]");
+    if (!(m0 > 0 && m0 < 2)) return fail(DWF_EINVAL, "m0 must be in (0, 2)");
+    if (!std::isfinite(mq)) return fail(DWF_EINVAL, "mq must be finite");
+    for (int s = 0; s < Ns; ++s) {
+        if (!(omega[s] > 0) || !std::isfinite(omega[s])) return fail(DWF_EINVAL, "omega_s must be > 0");
+        if (!std::isfinite(sigma[s])) return fail(DWF_EINVAL, "sigma_s must be finite");
+    }
+    long V4 = (long)dims[0] * dims[1] * dims[2] * dims[3];
+    if (V4 / 2 * Ns > (1L << 30)) return fail(DWF_EINVAL, "lattice too large");
+    {
+        std::vector<double> tmp;
+        std::string why;
+        if (!build_tables(Ns, m0, mq, sigma, omega, tmp, why)) return fail(DWF_EINVAL, why);
+    }
+    std::unique_ptr<dwf_ctx> c(new dwf_ctx);
+    for (int i = 0; i < 4; ++i) c->dims[i] = dims[i];
+    c->Ns = Ns;
+    c->m0 = m0;
+    c->mq = mq;
+    c->sigma.assign(sigma, sigma + Ns);
+    c->omega.assign(omega, omega + Ns);
+    if (opts)
+        c->opts = *opts;
+    else
+        dwf_default_opts(&c->opts);
+    c->device = c->opts.device;
+    c->V4 = V4;
+    c->V4h = V4 / 2;
+    c->V5h = c->V4h * Ns;
+    // workgroups of G 4D sites x Ns slices, at most 256 lanes
+    int G = c->opts.sites_per_block;
+    if (G < 0 || G * Ns > 256) return fail(DWF_EINVAL, "sites_per_block * Ns must be <= 256");
+    c->G32 = G > 0 ? G : std::min(64, std::max(1, 256 / Ns));
+    c->G64 = G > 0 ? std::max(1, G / 2) : std::min(32, std::max(1, 128 / Ns));
+
+    DWF_HIP(hipSetDevice(c->device));
+    DWF_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    int rc;
+    const size_t nl = (size_t)c->V4h * 8;
+    for (int par = 0; par < 2; ++par) {
+        if ((rc = c->links[par][LINK_D18].alloc(nl * 18 * sizeof(double)))) return rc;
+        if ((rc = c->links[par][LINK_S18].alloc(nl * 18 * sizeof(float)))) return rc;
+        if ((rc = c->links[par][LINK_S12].alloc(nl * 12 * sizeof(float)))) return rc;
+        if ((rc = c->links[par][LINK_H12].alloc(nl * 12 * sizeof(_Float16)))) return rc;
+    }
+    {
+        DevBuf g;
+        if ((rc = g.alloc((size_t)V4 * 4 * 18 * sizeof(double)))) return rc;
+        DWF_HIP(hipMemcpyAsync(g.p, gauge, (size_t)V4 * 4 * 18 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        DWF_HIP(pack_links(c.get(), g.as<double>(), c->stream));
+        DWF_HIP(hipStreamSynchronize(c->stream));
+    }
+    c->table_set(mq, &rc);
+    if (rc) return rc;
+    *out = c.release();
+    return DWF_OK;
+}
+
+void dwf_destroy(dwf_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    hipStream_t s = c->stream;
+    delete c;
+    if (s) (void)hipStreamDestroy(s);
+}
+
+int dwf_apply_dev(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs, void* stream) {
+    g_err.clear();
+    if (!c || !in_dev || !out_dev) return fail(DWF_EINVAL, "NULL context or buffer");
+    if (op < DWF_OP_DW || op > DWF_OP_DDAG) return fail(DWF_EINVAL, "unknown operator");
+    if (prec < DWF_PREC_FP64 || prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "unknown precision");
+    if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
+    std::lock_guard<std::mutex> lk(c->mtx);
+    DWF_HIP(hipSetDevice(c->device));
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    int rc = apply_op(c, op, prec, in_dev, out_dev, nrhs, s);
+    if (rc) return rc;
+    DWF_HIP(hipStreamSynchronize(s));
+    return DWF_OK;
+}
+
+int dwf_apply(dwf_ctx* c, int op, int prec, const double* in, double* out, int nrhs) {
+    g_err.clear();
+    if (!c || !in || !out) return fail(DWF_EINVAL, "NULL context or buffer");
+    if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
+    size_t n = (size_t)nrhs * c->V4 * c->Ns * 24 * sizeof(double);
+    DWF_HIP(hipSetDevice(c->device));
+    DevBuf din, dout;
+    int rc;
+    if ((rc = din.alloc(n)) || (rc = dout.alloc(n))) return rc;
+    DWF_HIP(hipMemcpy(din.p, in, n, hipMemcpyHostToDevice));
+    rc = dwf_apply_dev(c, op, prec, din.as<double>(), dout.as<double>(), nrhs, nullptr);
+    if (rc) return rc;
+    DWF_HIP(hipMemcpy(out, dout.p, n, hipMemcpyDeviceToHost));
+    return DWF_OK;
+}
+
+int dwf_solve_dev(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params* params,
+                  dwf_solve_stats* stats, void* stream) {
+    g_err.clear();
+    if (!c || !b_dev || !x_dev) return fail(DWF_EINVAL, "NULL context or buffer");
+    if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
+    dwf_solve_params p;
+    if (params)
+        p = *params;
+    else
+        dwf_default_params(&p);
+    if (!(p.tol > 0)) return fail(DWF_EINVAL, "tol must be > 0");
+    if (p.inner_prec < DWF_PREC_FP64 || p.inner_prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "bad inner_prec");
+    if (p.maxiter < 1) return fail(DWF_EINVAL, "maxiter must be >= 1");
+    std::lock_guard<std::mutex> lk(c->mtx);
+    DWF_HIP(hipSetDevice(c->device));
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    return solve(c, b_dev, x_dev, nrhs, p, stats, s, nullptr);
+}
+
+int dwf_time_kernels(dwf_ctx* c, const dwf_solve_params* params, int nrhs, int launches, double ms[5],
+                     double bytes[5]) {
+    g_err.clear();
+    if (!c || !ms || !bytes) return fail(DWF_EINVAL, "NULL argument");
+    if (nrhs < 1 || launches < 1) return fail(DWF_EINVAL, "nrhs and launches must be >= 1");
+    dwf_solve_params p;
+    if (params)
+        p = *params;
+    else
+        dwf_default_params(&p);
+    std::lock_guard<std::mutex> lk(c->mtx);
+    DWF_HIP(hipSetDevice(c->device));
+    return time_inner_kernels(c, p, nrhs, launches, ms, bytes);
+}
+
+int dwf_solve(dwf_ctx* c, const double* b, double* x, int nrhs, const dwf_solve_params* params,
+              dwf_solve_stats* stats) {
+    g_err.clear();
+    if (!c || !b || !x) return fail(DWF_EINVAL, "NULL context or buffer");
+    if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
+    size_t n = (size_t)nrhs * c->V4 * c->Ns * 24 * sizeof(double);
+    DWF_HIP(hipSetDevice(c->device));
+    DevBuf db, dx;
+    int rc;
+    if ((rc = db.alloc(n)) || (rc = dx.alloc(n))) return rc;
+    DWF_HIP(hipMemcpy(db.p, b, n, hipMemcpyHostToDevice));
+    if (params && params->use_guess) DWF_HIP(hipMemcpy(dx.p, x, n, hipMemcpyHostToDevice));
+    rc = dwf_solve_dev(c, db.as<double>(), dx.as<double>(), nrhs, params, stats, nullptr);
+    if (rc != DWF_OK && rc != DWF_ENOCONV) return rc;
+    DWF_HIP(hipMemcpy(x, dx.p, n, hipMemcpyDeviceToHost));
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,757 @@
+// dwf_device.h -- device-side building blocks of the gfx950 domain-wall
+// stencil: field accessors for the structure-of-arrays spinor layout, gauge
+// link formats with LDS staging, the spin-projected Wilson hop (Eq. (14)),
+// the dense per-4D-site fifth-dimension matrix (M5 of Eq. (8) and friends)
+// and the fused kernel template that strings them together with a
+// prologue/epilogue and a deterministic block reduction.
+//
+// Device layouts (one parity of the 4D checkerboard per "half field"):
+//   half 4D index  h4 = (x + Lx (y + Ly (z + Lz t))) / 2     (Lx even)
+//   half 5D index  i5 = s + Ns * h4                          (s fastest)
+//   FP64 spinor : double2 [12][stride]   block j = complex component j
+//   FP32 spinor : float4  [6][stride]    block j = complex components 2j, 2j+1
+//   FP16 spinor : 8 x binary16 [3][stride] + float norm[stride]
+//                 (value = half * norm, norm = max |component| of the site)
+//   complex component k = 3 * spin + colour; spins 0,1 are the + chirality
+//   (gamma_5 = diag(1,1,-1,-1) in the chiral basis).
+//   Gauge links, per output parity: [h4][8][n] with entries 0..3 the forward
+//   links U_mu(x) and 4..7 the backward links U_mu(x - mu)^dag, each a
+//   row-major 3x3 complex matrix (n = 18) or its first two rows (n = 12).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dwf {
+
+// ---------------------------------------------------------------------------
+// spinor fields
+// ---------------------------------------------------------------------------
+
+struct FD {  // FP64 storage and arithmetic
+    using real = double;
+    double2* p;
+    long stride;   // elements per component block
+    long rstride;  // elements between right-hand sides
+    __device__ __forceinline__ void load(int rhs, long i, double* v) const {
+        const double2* q = p + rhs * rstride + i;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) {
+            double2 a = q[j * stride];
+            v[2 * j] = a.x;
+            v[2 * j + 1] = a.y;
+        }
+    }
+    __device__ __forceinline__ void store(int rhs, long i, const double* v) const {
+        double2* q = p + rhs * rstride + i;
+#pragma unroll
+        for (int j = 0; j < 12; ++j) q[j * stride] = make_double2(v[2 * j], v[2 * j + 1]);
+    }
+    __device__ __forceinline__ void load(int rhs, long i, float* v) const {
+        double t[24];
+        load(rhs, i, t);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) v[k] = (float)t[k];
+    }
+    __device__ __forceinline__ void store(int rhs, long i, const float* v) const {
+        double t[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) t[k] = v[k];
+        store(rhs, i, t);
+    }
+};
+
+struct FS {  // FP32 storage
+    using real = float;
+    float4* p;
+    long stride;
+    long rstride;
+    __device__ __forceinline__ void load(int rhs, long i, float* v) const {
+        const float4* q = p + rhs * rstride + i;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            float4 a = q[j * stride];
+            v[4 * j] = a.x;
+            v[4 * j + 1] = a.y;
+            v[4 * j + 2] = a.z;
+            v[4 * j + 3] = a.w;
+        }
+    }
+    __device__ __forceinline__ void store(int rhs, long i, const float* v) const {
+        float4* q = p + rhs * rstride + i;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) q[j * stride] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+    }
+    __device__ __forceinline__ void load(int rhs, long i, double* v) const {
+        float t[24];
+        load(rhs, i, t);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) v[k] = t[k];
+    }
+    __device__ __forceinline__ void store(int rhs, long i, const double* v) const {
+        float t[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) t[k] = (float)v[k];
+        store(rhs, i, t);
+    }
+};
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+
+struct FH {  // binary16 storage with one FP32 scale per 5D site; FP32 arithmetic
+    using real = float;
+    uint4* p;
+    float* nrm;
+    long stride;
+    long rstride;   // data elements between right-hand sides
+    long nrstride;  // norm elements between right-hand sides
+    __device__ __forceinline__ void load(int rhs, long i, float* v) const {
+        const uint4* q = p + rhs * rstride + i;
+        float n = nrm[rhs * nrstride + i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            uint4 a = q[j * stride];
+            half8_t h = __builtin_bit_cast(half8_t, a);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[8 * j + k] = (float)h[k] * n;
+        }
+    }
+    __device__ __forceinline__ void store(int rhs, long i, const float* v) const {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
+        float inv = m > 0.f ? 1.f / m : 0.f;
+        uint4* q = p + rhs * rstride + i;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            half8_t h;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) h[k] = (_Float16)(v[8 * j + k] * inv);
+            q[j * stride] = __builtin_bit_cast(uint4, h);
+        }
+        nrm[rhs * nrstride + i] = m;
+    }
+    __device__ __forceinline__ void load(int rhs, long i, double* v) const {
+        float t[24];
+        load(rhs, i, t);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) v[k] = t[k];
+    }
+    __device__ __forceinline__ void store(int rhs, long i, const double* v) const {
+        float t[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) t[k] = (float)v[k];
+        store(rhs, i, t);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// gauge links: LDS staging of the 8 links of every site of a workgroup
+// ---------------------------------------------------------------------------
+
+template <class Real>
+struct LdsLink {
+    static constexpr int STR = sizeof(Real) == 4 ? 20 : 18;  // 16-byte aligned rows
+};
+
+template <class Real>
+__device__ __forceinline__ void su3_third_row(Real* u) {
+    // row2 = conj(row0 x row1)
+#define RE(a, b) u[2 * (3 * (a) + (b))]
+#define IM(a, b) u[2 * (3 * (a) + (b)) + 1]
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+        Real cr = RE(0, b1) * RE(1, b2) - IM(0, b1) * IM(1, b2) - (RE(0, b2) * RE(1, b1) - IM(0, b2) * IM(1, b1));
+        Real ci = RE(0, b1) * IM(1, b2) + IM(0, b1) * RE(1, b2) - (RE(0, b2) * IM(1, b1) + IM(0, b2) * RE(1, b1));
+        RE(2, b) = cr;
+        IM(2, b) = -ci;
+    }
+#undef RE
+#undef IM
+}
+
+struct LinkD18 {
+    using real = double;
+    const double* p;  // [h4][8][18]
+    __device__ __forceinline__ void stage(double* lds, long site0, int nsites, int tid, int T) const {
+        const double2* src = (const double2*)(p + site0 * 8 * 18);
+        int n2 = nsites * 8 * 9;
+        for (int i = tid; i < n2; i += T) {
+            double2 q = src[i];
+            lds[2 * i] = q.x;
+            lds[2 * i + 1] = q.y;
+        }
+    }
+};
+
+struct LinkS18 {
+    using real = float;
+    const float* p;  // [h4][8][18]
+    __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T) const {
+        const float2* src = (const float2*)(p + site0 * 8 * 18);
+        int n2 = nsites * 8 * 9;
+        for (int i = tid; i < n2; i += T) {
+            int l = i / 9, c = i - 9 * l;
+            float2 q = src[i];
+            lds[l * 20 + 2 * c] = q.x;
+            lds[l * 20 + 2 * c + 1] = q.y;
+        }
+    }
+};
+
+struct LinkS12 {
+    using real = float;
+    const float* p;  // [h4][8][12]
+    __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T) const {
+        const float4* src = (const float4*)(p + site0 * 8 * 12);
+        int nl = nsites * 8;
+        for (int l = tid; l < nl; l += T) {
+            float u[18];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                float4 q = src[3 * l + j];
+                u[4 * j] = q.x; u[4 * j + 1] = q.y; u[4 * j + 2] = q.z; u[4 * j + 3] = q.w;
+            }
+            su3_third_row(u);
+#pragma unroll
+            for (int k = 0; k < 18; ++k) lds[l * 20 + k] = u[k];
+        }
+    }
+};
+
+struct LinkH12 {
+    using real = float;
+    const _Float16* p;  // [h4][8][12]
+    __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T) const {
+        const uint2* src = (const uint2*)(p + site0 * 8 * 12);
+        int nl = nsites * 8;
+        typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+        for (int l = tid; l < nl; l += T) {
+            float u[18];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                half4_t h = __builtin_bit_cast(half4_t, src[3 * l + j]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) u[4 * j + k] = (float)h[k];
+            }
+            su3_third_row(u);
+#pragma unroll
+            for (int k = 0; k < 18; ++k) lds[l * 20 + k] = u[k];
+        }
+    }
+};
+
+struct LinkNone {
+    using real = double;
+};
+
+// ---------------------------------------------------------------------------
+// geometry and workgroup mapping
+// ---------------------------------------------------------------------------
+
+struct Geom {
+    int Lx, Ly, Lz, Lt;
+    int Lxh;       // Lx / 2
+    int Ns;
+    int G;         // 4D sites per workgroup
+    int V4h;       // 4D sites per parity
+    int out_parity;
+    int antiper;   // 1: links crossing the t boundary carry a factor -1
+    int nblocks;
+    int xcd;       // 1: map consecutive lattice blocks onto one XCD
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  Map dispatch id -> lattice block so that every XCD
+// walks one contiguous slab of the lattice (neighbour re-reads then hit the
+// same L2).  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_remap(int b, int nb, int on) {
+    if (!on) return b;
+    const int NX = 8;
+    int q = nb / NX, r = nb - q * NX;
+    int x = b % NX, idx = b / NX;
+    return x < r ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
+}
+
+// ---------------------------------------------------------------------------
+// Wilson hop along one direction, spin projected (Eq. (14)):
+//   acc += (1 + SIG gamma_MU) U psi,  SIG = -1 forward, +1 backward.
+// In the chiral basis (1 + SIG gamma_MU) psi is fixed by two spin components
+// h0, h1; U multiplies only those and the lower two are rebuilt from U h.
+// ---------------------------------------------------------------------------
+
+template <int MU, int SIG, class Real>
+__device__ __forceinline__ void hop_dir(const Real* __restrict__ psi, const Real* __restrict__ U,
+                                        Real sc, Real* __restrict__ acc) {
+    Real h0[6], h1[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const Real p0r = psi[2 * a], p0i = psi[2 * a + 1];
+        const Real p1r = psi[2 * (3 + a)], p1i = psi[2 * (3 + a) + 1];
+        const Real p2r = psi[2 * (6 + a)], p2i = psi[2 * (6 + a) + 1];
+        const Real p3r = psi[2 * (9 + a)], p3i = psi[2 * (9 + a) + 1];
+        if (MU == 0) {  // h0 = p0 - SIG i p3, h1 = p1 - SIG i p2
+            h0[2 * a] = p0r + SIG * p3i; h0[2 * a + 1] = p0i - SIG * p3r;
+            h1[2 * a] = p1r + SIG * p2i; h1[2 * a + 1] = p1i - SIG * p2r;
+        } else if (MU == 1) {  // h0 = p0 - SIG p3, h1 = p1 + SIG p2
+            h0[2 * a] = p0r - SIG * p3r; h0[2 * a + 1] = p0i - SIG * p3i;
+            h1[2 * a] = p1r + SIG * p2r; h1[2 * a + 1] = p1i + SIG * p2i;
+        } else if (MU == 2) {  // h0 = p0 - SIG i p2, h1 = p1 + SIG i p3
+            h0[2 * a] = p0r + SIG * p2i; h0[2 * a + 1] = p0i - SIG * p2r;
+            h1[2 * a] = p1r - SIG * p3i; h1[2 * a + 1] = p1i + SIG * p3r;
+        } else {  // h0 = p0 + SIG p2, h1 = p1 + SIG p3
+            h0[2 * a] = p0r + SIG * p2r; h0[2 * a + 1] = p0i + SIG * p2i;
+            h1[2 * a] = p1r + SIG * p3r; h1[2 * a + 1] = p1i + SIG * p3i;
+        }
+    }
+    Real u0[6], u1[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        Real r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const Real ur = U[2 * (3 * a + b)], ui = U[2 * (3 * a + b) + 1];
+            r0 += ur * h0[2 * b] - ui * h0[2 * b + 1];
+            i0 += ur * h0[2 * b + 1] + ui * h0[2 * b];
+            r1 += ur * h1[2 * b] - ui * h1[2 * b + 1];
+            i1 += ur * h1[2 * b + 1] + ui * h1[2 * b];
+        }
+        if (MU == 3) { r0 *= sc; i0 *= sc; r1 *= sc; i1 *= sc; }
+        u0[2 * a] = r0; u0[2 * a + 1] = i0;
+        u1[2 * a] = r1; u1[2 * a + 1] = i1;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const Real r0 = u0[2 * a], i0 = u0[2 * a + 1], r1 = u1[2 * a], i1 = u1[2 * a + 1];
+        acc[2 * a] += r0; acc[2 * a + 1] += i0;
+        acc[2 * (3 + a)] += r1; acc[2 * (3 + a) + 1] += i1;
+        Real c2r, c2i, c3r, c3i;
+        if (MU == 0) {  // c2 = SIG i u1, c3 = SIG i u0
+            c2r = -SIG * i1; c2i = SIG * r1; c3r = -SIG * i0; c3i = SIG * r0;
+        } else if (MU == 1) {  // c2 = SIG u1, c3 = -SIG u0
+            c2r = SIG * r1; c2i = SIG * i1; c3r = -SIG * r0; c3i = -SIG * i0;
+        } else if (MU == 2) {  // c2 = SIG i u0, c3 = -SIG i u1
+            c2r = -SIG * i0; c2i = SIG * r0; c3r = SIG * i1; c3i = -SIG * r1;
+        } else {  // c2 = SIG u0, c3 = SIG u1
+            c2r = SIG * r0; c2i = SIG * i0; c3r = SIG * r1; c3i = SIG * i1;
+        }
+        acc[2 * (6 + a)] += c2r; acc[2 * (6 + a) + 1] += c2i;
+        acc[2 * (9 + a)] += c3r; acc[2 * (9 + a) + 1] += c3i;
+    }
+}
+
+// Neighbour half indices of 4D half site h4 (of parity par):
+// nb[0..3] = x + mu, nb[4..7] = x - mu; tpos = 1 at t = Lt-1, 2 at t = 0.
+__device__ __forceinline__ void neighbours(const Geom& g, int h4, int par, int* nb, int& tfw, int& tbw) {
+    int xh = h4 % g.Lxh;
+    int r = h4 / g.Lxh;
+    int y = r % g.Ly;
+    r /= g.Ly;
+    int z = r % g.Lz;
+    int t = r / g.Lz;
+    int x = 2 * xh + ((y + z + t + par) & 1);
+    int xp = x + 1 == g.Lx ? 0 : x + 1, xm = x == 0 ? g.Lx - 1 : x - 1;
+    int yp = y + 1 == g.Ly ? 0 : y + 1, ym = y == 0 ? g.Ly - 1 : y - 1;
+    int zp = z + 1 == g.Lz ? 0 : z + 1, zm = z == 0 ? g.Lz - 1 : z - 1;
+    int tp = t + 1 == g.Lt ? 0 : t + 1, tm = t == 0 ? g.Lt - 1 : t - 1;
+    int row = y + g.Ly * (z + g.Lz * t);
+    nb[0] = (xp >> 1) + g.Lxh * row;
+    nb[4] = (xm >> 1) + g.Lxh * row;
+    nb[1] = xh + g.Lxh * (yp + g.Ly * (z + g.Lz * t));
+    nb[5] = xh + g.Lxh * (ym + g.Ly * (z + g.Lz * t));
+    nb[2] = xh + g.Lxh * (y + g.Ly * (zp + g.Lz * t));
+    nb[6] = xh + g.Lxh * (y + g.Ly * (zm + g.Lz * t));
+    nb[3] = xh + g.Lxh * (y + g.Ly * (z + g.Lz * tp));
+    nb[7] = xh + g.Lxh * (y + g.Ly * (z + g.Lz * tm));
+    tfw = (t == g.Lt - 1);
+    tbw = (t == 0);
+}
+
+template <class Real, class F>
+__device__ __forceinline__ void hop_site(const F& in, int rhs, int s, int Ns, const int* nb,
+                                         const Real* __restrict__ lk, Real sf, Real sb, Real* acc) {
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] = 0;
+    constexpr int LS = LdsLink<Real>::STR;
+    Real psi[24];
+    Real U[18];
+#define DWF_HOP(MU)                                                        \
+    {                                                                      \
+        in.load(rhs, (long)nb[MU] * Ns + s, psi);                          \
+        _Pragma("unroll") for (int k = 0; k < 18; ++k) U[k] = lk[(MU) * LS + k]; \
+        hop_dir<MU, -1>(psi, U, sf, acc);                                  \
+        in.load(rhs, (long)nb[4 + (MU)] * Ns + s, psi);                    \
+        _Pragma("unroll") for (int k = 0; k < 18; ++k) U[k] = lk[(4 + (MU)) * LS + k]; \
+        hop_dir<MU, +1>(psi, U, sb, acc);                                  \
+    }
+    DWF_HOP(0)
+    DWF_HOP(1)
+    DWF_HOP(2)
+    DWF_HOP(3)
+#undef DWF_HOP
+#pragma unroll
+    for (int k = 0; k < 24; ++k) acc[k] *= (Real)-0.5;
+}
+
+// ---------------------------------------------------------------------------
+// block reduction (deterministic: fixed shuffle tree, fixed wave order)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    int tid = threadIdx.x, w = tid >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    if ((tid & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (tid == 0)
+        for (int i = 0; i < nw; ++i) s += red[i];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+// ---------------------------------------------------------------------------
+// the fused kernel
+//   phase 1: v = hop(in) on every (site, s) lane     [HOP]
+//            v = prologue(site, s)                   [!HOP]
+//   phase 2: v_s = sum_t T[ch][s][t] v_t per 4D site  [MIX]  (LDS transpose)
+//   phase 3: epilogue(site, s, v) -> norm contribution, block-reduced
+// One workgroup covers G consecutive 4D half sites x all Ns slices, lane
+// (sl, s) = (tid / Ns, tid % Ns), so the SoA loads of consecutive lanes are
+// consecutive 16-byte vectors and the G x 8 links are staged once in LDS
+// and shared by the Ns slices (and by every right-hand side).
+// ---------------------------------------------------------------------------
+
+struct KOpt {
+    const int* live;       // per right-hand side; NULL = always run
+    double* partials;      // [nrhs][nblocks] block sums when the epilogue reduces
+    int nrhs;
+    long table_rstride;    // elements between right-hand sides' tables (0 = shared)
+};
+
+template <class Real>
+__host__ __device__ inline int hbuf_site_stride(int Ns) {
+    return Ns * 24 + (sizeof(Real) == 4 ? 12 : 6);
+}
+
+template <class Real>
+__host__ __device__ inline size_t kernel_smem(int G, int Ns, bool hop, bool mix) {
+    size_t b = 0;
+    if (hop) b += (size_t)G * 8 * LdsLink<Real>::STR * sizeof(Real);
+    if (mix) b += (size_t)G * hbuf_site_stride<Real>(Ns) * sizeof(Real);
+    b = (b + 15) & ~(size_t)15;
+    b += 16 * sizeof(double);
+    return b;
+}
+
+template <class Real, class F, class LF, int NSMAX, bool HOP, bool MIX, class Pro, class Epi>
+__global__ void __launch_bounds__(256)
+k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, KOpt o) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int LS = LdsLink<Real>::STR;
+    const int Ns = g.Ns;
+    const int tid = threadIdx.x, T = blockDim.x;
+
+    if (o.live) {  // uniform early exit when no right-hand side is live
+        int any = 0;
+        for (int r = 0; r < o.nrhs; ++r) any |= o.live[r];
+        if (!any) return;
+    }
+
+    Real* lk = (Real*)smem;
+    Real* hb = lk + (HOP ? g.G * 8 * LS : 0);
+    size_t off = (HOP ? (size_t)g.G * 8 * LS * sizeof(Real) : 0) +
+                 (MIX ? (size_t)g.G * hbuf_site_stride<Real>(Ns) * sizeof(Real) : 0);
+    off = (off + 15) & ~(size_t)15;
+    double* red = (double*)(smem + off);
+
+    const int lb = xcd_remap(blockIdx.x, g.nblocks, g.xcd);
+    const long site0 = (long)lb * g.G;
+    const int nsites = (int)min((long)g.G, (long)g.V4h - site0);
+    const int sl = tid / Ns, s = tid - sl * Ns;
+    const bool act = sl < nsites;
+    const long h4 = site0 + sl;
+    const long i5 = (long)s + (long)Ns * h4;
+    const int hs = hbuf_site_stride<Real>(Ns);
+
+    int nb[8];
+    Real sf = 1, sb = 1;
+    if constexpr (HOP) {
+        links.stage(lk, site0, nsites, tid, T);
+        if (act) {
+            int tf, tb;
+            neighbours(g, (int)h4, g.out_parity, nb, tf, tb);
+            if (g.antiper) {
+                sf = tf ? (Real)-1 : (Real)1;
+                sb = tb ? (Real)-1 : (Real)1;
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int rhs = 0; rhs < o.nrhs; ++rhs) {
+        if (o.live && !o.live[rhs]) continue;
+        Real v[24];
+        if (act) {
+            if constexpr (HOP)
+                hop_site<Real>(in, rhs, s, Ns, nb, lk + sl * 8 * LS, sf, sb, v);
+            else
+                pro(rhs, i5, v);
+        }
+        if constexpr (MIX) {
+            if (act) {
+                Real* dst = hb + sl * hs + s * 24;
+#pragma unroll
+                for (int k = 0; k < 24; ++k) dst[k] = v[k];
+            }
+            __syncthreads();
+            // columns (chirality ch, site, real component c of that chirality);
+            // every wave handles columns of one chirality so that the table
+            // entries are wave-uniform (scalar loads).
+            const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+            const int lane = tid & 63;
+            const int nwaves = (T + 63) >> 6;
+            const int ncol = nsites * 12;
+            const int nch = (ncol + 63) >> 6;
+            const Real* tb = table + rhs * o.table_rstride;
+            for (int c = wave; c < 2 * nch; c += nwaves) {
+                const int ch = c / nch;
+                const int col = (c - ch * nch) * 64 + lane;
+                if (col < ncol) {
+                    const int cs = col / 12, cc = col - cs * 12;
+                    Real* base = hb + cs * hs + ch * 12 + cc;
+                    const Real* M = tb + ch * Ns * Ns;
+                    Real h[NSMAX];
+#pragma unroll
+                    for (int t = 0; t < NSMAX; ++t)
+                        if (t < Ns) h[t] = base[t * 24];
+#pragma unroll
+                    for (int ss = 0; ss < NSMAX; ++ss) {
+                        if (ss < Ns) {
+                            Real acc = 0;
+#pragma unroll
+                            for (int t = 0; t < NSMAX; ++t)
+                                if (t < Ns) acc += M[ss * Ns + t] * h[t];
+                            base[ss * 24] = acc;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (act) {
+                const Real* src = hb + sl * hs + s * 24;
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v[k] = src[k];
+            }
+        }
+        double part = 0;
+        if (act) part = epi(rhs, i5, v);
+        if constexpr (Epi::kReduce) {
+            double tot = block_sum(part, red);
+            if (tid == 0) o.partials[(long)rhs * gridDim.x + blockIdx.x] = tot;
+        }
+        if constexpr (MIX) __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-right-hand-side CG state (device arrays of length nrhs)
+// ---------------------------------------------------------------------------
+
+struct CgState {
+    double* rr;         // |r|^2 of the current iterate
+    double* uu;         // |u|^2 = (p, C C^dag p)
+    double* alpha;
+    double* beta;
+    double* rr_target;  // the inner solve stops once rr <= rr_target
+    double* aux;        // generic reduction results
+    int* live;          // 1 while the inner solve runs
+    int* iters;         // inner iterations done (all cycles)
+    int* status;        // 0 running, 1 converged, 2 breakdown, 3 iteration cap, 4 diverged
+    int* maxiter;
+};
+
+// ---------------------------------------------------------------------------
+// prologues (phase 1 without a hop)
+// ---------------------------------------------------------------------------
+
+template <class F>
+struct ProLoad {
+    F f;
+    template <class Real>
+    __device__ __forceinline__ void operator()(int rhs, long i, Real* v) const { f.load(rhs, i, v); }
+};
+
+// CG direction update, Algorithm 1: p = r + beta p (or p = r when reset[rhs]).
+template <class FR, class FP>
+struct ProCgE {
+    FR r;
+    FP p;
+    const double* beta;
+    const int* reset;  // per right-hand side; NULL = never reset
+    template <class Real>
+    __device__ __forceinline__ void operator()(int rhs, long i, Real* v) const {
+        r.load(rhs, i, v);
+        if (!(reset && reset[rhs])) {
+            Real b = (Real)beta[rhs];
+            Real q[24];
+            p.load(rhs, i, q);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] += b * q[k];
+        }
+        p.store(rhs, i, v);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// epilogues (phase 3); return the lane's contribution to the block sum
+// ---------------------------------------------------------------------------
+
+template <class Real>
+__device__ __forceinline__ double norm2_24(const Real* v) {
+    Real s = 0;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) s += v[k] * v[k];
+    return (double)s;
+}
+
+template <class F, bool RED = false>
+struct EpiStore {
+    static constexpr bool kReduce = RED;
+    F out;
+    template <class Real>
+    __device__ __forceinline__ double operator()(int rhs, long i, Real* v) const {
+        out.store(rhs, i, v);
+        return RED ? norm2_24(v) : 0.0;
+    }
+};
+
+// stores nothing; returns |v|^2
+struct EpiNorm {
+    static constexpr bool kReduce = true;
+    template <class Real>
+    __device__ __forceinline__ double operator()(int, long, Real* v) const { return norm2_24(v); }
+};
+
+// out = ca * a + cv * (g5 ? gamma_5 v : v)
+template <class FA, class FO, bool RED, bool G5>
+struct EpiLin {
+    static constexpr bool kReduce = RED;
+    FA a;
+    FO out;
+    double ca, cv;
+    template <class Real>
+    __device__ __forceinline__ double operator()(int rhs, long i, Real* v) const {
+        Real w[24];
+        a.load(rhs, i, w);
+        const Real A = (Real)ca, B = (Real)cv;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            Real vk = (G5 && k >= 12) ? -v[k] : v[k];
+            w[k] = A * w[k] + B * vk;
+        }
+        out.store(rhs, i, w);
+        return RED ? norm2_24(w) : 0.0;
+    }
+};
+
+// CG kernel B: u = p - gamma_5 v (v = D^OE t2), returns |u|^2.
+template <class FP, class FU>
+struct EpiCgB {
+    static constexpr bool kReduce = true;
+    FP p;
+    FU u;
+    template <class Real>
+    __device__ __forceinline__ double operator()(int rhs, long i, Real* v) const {
+        Real w[24];
+        p.load(rhs, i, w);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) w[k] = k < 12 ? w[k] - v[k] : w[k] + v[k];
+        u.store(rhs, i, w);
+        return norm2_24(w);
+    }
+};
+
+// CG kernel D: q = u - v (v = M5 D^OE t3), y += alpha u, r -= alpha q; returns |r|^2.
+template <class FU, class FR, class FY>
+struct EpiCgD {
+    static constexpr bool kReduce = true;
+    FU u;
+    FR r;
+    FY y;
+    const double* alpha;
+    template <class Real>
+    __device__ __forceinline__ double operator()(int rhs, long i, Real* v) const {
+        const Real a = (Real)alpha[rhs];
+        Real uu[24], w[24];
+        u.load(rhs, i, uu);
+        r.load(rhs, i, w);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) w[k] -= a * (uu[k] - v[k]);
+        r.store(rhs, i, w);
+        Real yy[24];
+        y.load(rhs, i, yy);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) yy[k] += a * uu[k];
+        y.store(rhs, i, yy);
+        return norm2_24(w);
+    }
+};
+
+// Outer step: rhat = b'' - (yhat - v) with v = M5 D^OE M5 D^EO yhat, i.e.
+// rhat = b'' - C yhat in FP64; stores the low-precision r = rhat and zeroes
+// the low-precision solution y; returns |rhat|^2.
+template <class FB, class FYH, class FR, class FY>
+struct EpiOuter {
+    static constexpr bool kReduce = true;
+    FB b2;
+    FYH yh;
+    FR r;
+    FY y;
+    __device__ __forceinline__ double operator()(int rhs, long i, double* v) const {
+        double bb[24], yy[24];
+        b2.load(rhs, i, bb);
+        yh.load(rhs, i, yy);
+        double s = 0;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            bb[k] = bb[k] - yy[k] + v[k];
+            s += bb[k] * bb[k];
+        }
+        r.store(rhs, i, bb);
+        double z[24];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) z[k] = 0;
+        y.store(rhs, i, z);
+        return s;
+    }
+};
+
+// True residual of the 5D operator on one parity:
+// res = b - (Xx + v) with v = D_w^{pq} (Y x)_q; returns |res|^2, stores nothing.
+template <class FB, class FX>
+struct EpiTrueRes {
+    static constexpr bool kReduce = true;
+    FB b;
+    FX xx;
+    __device__ __forceinline__ double operator()(int rhs, long i, double* v) const {
+        double bb[24], w[24];
+        b.load(rhs, i, bb);
+        xx.load(rhs, i, w);
+        double s = 0;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            double d = bb[k] - w[k] - v[k];
+            s += d * d;
+        }
+        return s;
+    }
+};
+
+}  // namespace dwf

@@ -1,0 +1,179 @@
+// ops.hip -- the operators of dwf_apply, built from the fused stencil kernel:
+// D_w (Eq. (2)), the hopping blocks D_w^EO / D_w^OE (Eq. (14)), M5 and M5^T
+// (Eq. (8)), the Schur complement C (Eq. (11)) and C^dag, C C^dag, and the
+// 5D operator D (Eq. (5)) and D^dag, each in FP64, FP32 or FP16 storage.
+#include "dwf_ctx.h"
+
+namespace dwf {
+
+template <class F>
+F fld(const HalfField& h);
+template <>
+FD fld<FD>(const HalfField& h) { return h.fd(); }
+template <>
+FS fld<FS>(const HalfField& h) { return h.fs(); }
+template <>
+FH fld<FH>(const HalfField& h) { return h.fh(); }
+
+template <class Real>
+const Real* tab(const TableSet* ts, int t, int Ns);
+template <>
+const double* tab<double>(const TableSet* ts, int t, int Ns) { return ts->t64(t, Ns); }
+template <>
+const float* tab<float>(const TableSet* ts, int t, int Ns) { return ts->t32(t, Ns); }
+
+namespace {
+
+enum { IN_E = 0, IN_O, OUT_E, OUT_O, T_E, T_O, T2_E, T2_O, NAPPLY };
+
+template <class Real, class F, class LF>
+struct Applier {
+    dwf_ctx* c;
+    const TableSet* ts;
+    Workspace* w;
+    LF lk[2];
+    KOpt o;
+    hipStream_t s;
+
+    Geom geom(int par) const { return c->geom(par, sizeof(Real) == 8); }
+    F f(int i) const { return fld<F>(w->f(i)); }
+    const Real* t(int which) const { return tab<Real>(ts, which, c->Ns); }
+
+    // out(par) = epi( hop(in) )
+    template <class Epi>
+    hipError_t hop(int par, int in, const Epi& epi) {
+        return launch_dwf<Real, F, LF, true, false, ProLoad<F>, Epi>(geom(par), f(in), lk[par], nullptr,
+                                                                     ProLoad<F>{f(in)}, epi, o, s);
+    }
+    // out(par) = epi( T hop(in) )
+    template <class Epi>
+    hipError_t hopmix(int par, int in, int table, const Epi& epi) {
+        return launch_dwf<Real, F, LF, true, true, ProLoad<F>, Epi>(geom(par), f(in), lk[par], t(table),
+                                                                    ProLoad<F>{f(in)}, epi, o, s);
+    }
+    // out(par) = epi( T in )
+    template <class Epi>
+    hipError_t local(int par, int in, int table, const Epi& epi) {
+        return launch_dwf<Real, F, LF, false, true, ProLoad<F>, Epi>(geom(par), f(in), lk[par], t(table),
+                                                                     ProLoad<F>{f(in)}, epi, o, s);
+    }
+    EpiStore<F> store(int i) const { return EpiStore<F>{f(i)}; }
+    EpiLin<F, F, false, false> lin(int a, int out, double ca, double cv) const {
+        return EpiLin<F, F, false, false>{f(a), f(out), ca, cv};
+    }
+
+    hipError_t zero(int i) { return half_zero(c, w->f(i), o.nrhs, s); }
+
+    hipError_t run(int op) {
+        hipError_t e = hipSuccess;
+#define CK(x)                         \
+    do {                              \
+        e = (x);                      \
+        if (e != hipSuccess) return e; \
+    } while (0)
+        const double dm = 4.0 - c->m0;
+        switch (op) {
+            case DWF_OP_HOP_EO:
+                CK(hop(0, IN_O, store(OUT_E)));
+                CK(zero(OUT_O));
+                break;
+            case DWF_OP_HOP_OE:
+                CK(hop(1, IN_E, store(OUT_O)));
+                CK(zero(OUT_E));
+                break;
+            case DWF_OP_DW:
+                CK(hop(0, IN_O, lin(IN_E, OUT_E, dm, 1.0)));
+                CK(hop(1, IN_E, lin(IN_O, OUT_O, dm, 1.0)));
+                break;
+            case DWF_OP_M5:
+            case DWF_OP_M5T: {
+                int tb = op == DWF_OP_M5 ? TB_M5 : TB_M5T;
+                CK(local(0, IN_E, tb, store(OUT_E)));
+                CK(local(1, IN_O, tb, store(OUT_O)));
+                break;
+            }
+            case DWF_OP_C:
+                CK(hopmix(0, IN_O, TB_M5, store(T_E)));
+                CK(hopmix(1, T_E, TB_M5, lin(IN_O, OUT_O, 1.0, -1.0)));
+                CK(zero(OUT_E));
+                break;
+            case DWF_OP_CDAG:
+            case DWF_OP_CCDAG: {
+                int dst = op == DWF_OP_CDAG ? OUT_O : T2_O;
+                CK(local(1, IN_O, TB_M5TG5, store(T_O)));
+                CK(hopmix(0, T_O, TB_M5T, store(T_E)));
+                CK(hop(1, T_E, EpiLin<F, F, false, true>{f(IN_O), f(dst), 1.0, -1.0}));
+                if (op == DWF_OP_CCDAG) {
+                    CK(hopmix(0, T2_O, TB_M5, store(T_E)));
+                    CK(hopmix(1, T_E, TB_M5, lin(T2_O, OUT_O, 1.0, -1.0)));
+                }
+                CK(zero(OUT_E));
+                break;
+            }
+            case DWF_OP_D:
+                for (int p = 0; p < 2; ++p) {
+                    CK(local(p, IN_E + p, TB_Y, store(T_E + p)));
+                    CK(local(p, IN_E + p, TB_X, store(T2_E + p)));
+                }
+                CK(hop(0, T_O, lin(T2_E, OUT_E, 1.0, 1.0)));
+                CK(hop(1, T_E, lin(T2_O, OUT_O, 1.0, 1.0)));
+                break;
+            case DWF_OP_DDAG:
+                for (int p = 0; p < 2; ++p) CK(local(p, IN_E + p, TB_G5, store(T_E + p)));   // g = g5 x
+                CK(hop(0, T_O, lin(T_E, T2_E, dm, 1.0)));                                   // w = D_w g
+                CK(hop(1, T_E, lin(T_O, T2_O, dm, 1.0)));
+                for (int p = 0; p < 2; ++p) CK(local(p, IN_E + p, TB_1MLT, store(T_E + p)));  // (1-L)^T x
+                for (int p = 0; p < 2; ++p) CK(local(p, T2_E + p, TB_YTG5, lin(T_E + p, OUT_E + p, 1.0, 1.0)));
+                break;
+            default:
+                return hipErrorInvalidValue;
+        }
+#undef CK
+        return e;
+    }
+};
+
+template <class Real, class F, class LF>
+int apply_impl(dwf_ctx* c, int op, int prec, LF e, LF o_, const double* in_dev, double* out_dev, int nrhs,
+               hipStream_t s) {
+    int rc;
+    const TableSet* ts = c->table_set(c->mq, &rc);
+    if (!ts) return rc;
+    std::string key = "apply:" + std::to_string(prec) + ":" + std::to_string(nrhs);
+    auto& slot = c->ws[key];
+    if (!slot) {
+        slot.reset(new Workspace);
+        if ((rc = slot->alloc(std::vector<int>(NAPPLY, prec), c->V5h, nrhs))) {
+            slot.reset();
+            return rc;
+        }
+    }
+    Workspace* w = slot.get();
+    Applier<Real, F, LF> A{c, ts, w, {e, o_}, KOpt{nullptr, nullptr, nrhs, 0}, s};
+    DWF_HIP(host_to_half(c, in_dev, nrhs, w->f(IN_E), w->f(IN_O), s));
+    hipError_t err = A.run(op);
+    if (err != hipSuccess) return fail(DWF_EDEVICE, std::string("operator kernels: ") + hipGetErrorString(err));
+    DWF_HIP(half_to_host(c, w->f(OUT_E), w->f(OUT_O), nrhs, out_dev, s));
+    return DWF_OK;
+}
+
+}  // namespace
+
+int apply_op(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs, hipStream_t s) {
+    switch (prec) {
+        case DWF_PREC_FP64:
+            return apply_impl<double, FD, LinkD18>(c, op, prec, LinkD18{c->links[0][LINK_D18].as<double>()},
+                                                   LinkD18{c->links[1][LINK_D18].as<double>()}, in_dev, out_dev,
+                                                   nrhs, s);
+        case DWF_PREC_FP32:
+            return apply_impl<float, FS, LinkS18>(c, op, prec, LinkS18{c->links[0][LINK_S18].as<float>()},
+                                                  LinkS18{c->links[1][LINK_S18].as<float>()}, in_dev, out_dev,
+                                                  nrhs, s);
+        default:
+            return apply_impl<float, FH, LinkH12>(c, op, prec, LinkH12{c->links[0][LINK_H12].as<_Float16>()},
+                                                  LinkH12{c->links[1][LINK_H12].as<_Float16>()}, in_dev, out_dev,
+                                                  nrhs, s);
+    }
+}
+
+}  // namespace dwf

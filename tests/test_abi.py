@@ -1,0 +1,104 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/dwf.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "dwf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dwf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    import paper_1101_0423_amd as dwf
+    L = dwf.lib()
+    names = declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(dwf.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", dwf.lib_path()], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(r" T " + n + r"$", out, flags=re.M), n
+
+
+def test_default_params():
+    import paper_1101_0423_amd as dwf
+    p = dwf.default_params()
+    assert p.tol == 1e-10 and p.inner_prec == dwf.PREC_FP32 and p.reliable == 1 and p.use_graph == 1
+
+
+def _create(dims=(4, 4, 4, 4), ns=4, m0=1.8, mq=0.1, sigma=None, omega=None, gauge=True):
+    import paper_1101_0423_amd as dwf
+    L = dwf.lib()
+    h = ctypes.c_void_p()
+    sigma = np.zeros(ns) if sigma is None else np.asarray(sigma, float)
+    omega = np.ones(ns) if omega is None else np.asarray(omega, float)
+    g = np.zeros(4 * 18 * int(np.prod(dims))) if gauge else None
+    dp = ctypes.POINTER(ctypes.c_double)
+    d = (ctypes.c_int * 4)(*dims)
+    rc = L.dwf_create(ctypes.byref(h), g.ctypes.data_as(dp) if gauge else None, d, ns, m0, mq,
+                      sigma.ctypes.data_as(dp), omega.ctypes.data_as(dp), None)
+    return rc, L.dwf_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(dims=(4, 4, 4, 3)), "even"),
+    (dict(dims=(4, 0, 4, 4)), "even"),
+    (dict(ns=0), "Ns"),
+    (dict(ns=33), "Ns"),
+    (dict(m0=0.0), "m0"),
+    (dict(m0=2.0), "m0"),
+    (dict(omega=[1, 1, 0, 1]), "omega"),
+    (dict(gauge=False), "NULL"),
+    # (1 + cL) singular: Ns = 1, 1 - kappa c = 0 with kappa = mq / (2 m0) = 0.1
+    (dict(ns=1, m0=1.0, mq=0.2, sigma=[10.0], omega=[1.0]), "singular"),
+])
+def test_create_rejects_bad_arguments(kw, msg):
+    import paper_1101_0423_amd as dwf
+    rc, err = _create(**kw)
+    assert rc == dwf.DWF_EINVAL
+    assert msg in err
+
+
+def test_x_singular_rejected():
+    """X = a + b L_+ with Ns = 1: a - kappa b = 0 makes X singular (Eq. (7))."""
+    import paper_1101_0423_amd as dwf
+    m0, om = 1.0, 1.0
+    a = (4 - m0) * om + 1            # = 4
+    # choose sigma so that b = (4 - m0) sigma - 1 and kappa = a / b
+    sigma = 1.0
+    b = (4 - m0) * sigma - 1         # = 2  -> kappa = 2 -> mq = 2 kappa m0 = 4
+    rc, err = _create(ns=1, m0=m0, mq=2 * (a / b) * m0, sigma=[sigma], omega=[om])
+    assert rc == dwf.DWF_EINVAL and "singular" in err
+
+
+def test_null_arguments_everywhere():
+    import paper_1101_0423_amd as dwf
+    L = dwf.lib()
+    assert L.dwf_apply(None, 0, 0, None, None, 1) == dwf.DWF_EINVAL
+    assert L.dwf_solve(None, None, None, 1, None, None) == dwf.DWF_EINVAL
+    assert L.dwf_solve_dev(None, None, None, 1, None, None, None) == dwf.DWF_EINVAL
+    assert L.dwf_apply_dev(None, 0, 0, None, None, 1, None) == dwf.DWF_EINVAL
+    L.dwf_destroy(None)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """The binding never falls back to anything: without libdwf.so it raises."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_1101_0423_amd.binding as b\n"
+        "b._LIB_PATH = %r\n"
+        "try:\n    b.lib()\nexcept ImportError as e:\n    print('RAISED', e)\n"
+    ) % (ROOT, str(tmp_path / "missing.so"))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True).stdout
+    assert "RAISED" in out

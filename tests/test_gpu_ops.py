@@ -1,0 +1,155 @@
+"""GPU operator parity: every dwf_apply operator against the FP64 oracle.
+
+Bars (norm-wise and element-wise relative to the oracle): FP64 1e-13, FP32
+1e-6, FP16 storage 2e-2 (binary16 keeps 11 significant bits per component
+relative to its site's largest component).  Shapes span several workgroups
+and a ragged last workgroup; the full 16^3x32x16 workload runs in the
+launch configuration the solver uses.
+"""
+import numpy as np
+import pytest
+
+import dwf_inputs as inp
+import oracle
+from _util import Problem, max_rel, on_parity, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-13, 1: 1e-6, 2: 2e-2}
+
+
+def problems():
+    rng = np.random.default_rng(77)
+    ns5_s, ns5_w = rng.uniform(0.2, 1.4, 5), rng.uniform(0.5, 1.5, 5)
+    return {
+        # 4^4 x 8 Shamir (the small configuration)
+        "shamir4": Problem.workload("shamir_4x4x4x4_ns8"),
+        # unequal extents, Ns = 5, sigma != omega, antiperiodic time: several
+        # workgroups with a ragged tail (V4h = 192 sites, 51 per FP32 workgroup)
+        "ragged": Problem((4, 6, 2, 8), 5, 1.6, 0.1, ns5_s, ns5_w, 0.5, 31, 32, antiperiodic=True),
+        # Ns = 16 optimal-DWF weights on 8^3 x 4
+        "odwf8": Problem((8, 8, 8, 4), 16, 1.8, 0.01, *(2 * [rng.uniform(0.5, 1.5, 16)]), 0.5, 33, 34),
+        # Ns = 1 and Ns = 32 edges
+        "ns1": Problem((4, 4, 2, 2), 1, 1.2, 0.3, [0.7], [1.3], 0.5, 35, 36),
+        "ns32": Problem((4, 2, 2, 4), 32, 1.8, 0.05, np.zeros(32), np.ones(32), 0.5, 37, 38),
+    }
+
+
+PROBS = problems()
+
+
+def oracle_op(P, op, psi):
+    import paper_1101_0423_amd as dwf
+    a = P.oargs()
+    U, dims, ns, m0, mq, sg, om = a
+    if op == dwf.OP_DW:
+        return oracle.dw(U, dims, ns, m0, psi, bct=P.bct)
+    if op == dwf.OP_HOP_EO:
+        return oracle.hop(U, dims, ns, 0, psi, bct=P.bct)
+    if op == dwf.OP_HOP_OE:
+        return oracle.hop(U, dims, ns, 1, psi, bct=P.bct)
+    if op in (dwf.OP_M5, dwf.OP_M5T):
+        mp, mm = oracle.m5(ns, m0, mq, sg, om)
+        if op == dwf.OP_M5T:
+            mp, mm = mp.T, mm.T
+        return oracle.apply_s(dims, ns, mp, mm, psi)
+    if op == dwf.OP_C:
+        return oracle.schur_c(*a, on_parity(psi, dims, 1), bct=P.bct)
+    if op == dwf.OP_CDAG:
+        return oracle.schur_cdag(*a, on_parity(psi, dims, 1), bct=P.bct)
+    if op == dwf.OP_CCDAG:
+        t = oracle.schur_cdag(*a, on_parity(psi, dims, 1), bct=P.bct)
+        return oracle.schur_c(*a, t, bct=P.bct)
+    if op == dwf.OP_D:
+        return oracle.d5(*a, psi, bct=P.bct)
+    if op == dwf.OP_DDAG:
+        return oracle.d5dag(*a, psi, bct=P.bct)
+    raise ValueError(op)
+
+
+OPS = list(range(10))
+OP_NAMES = ["DW", "HOP_EO", "HOP_OE", "M5", "M5T", "C", "CDAG", "CCDAG", "D", "DDAG"]
+
+
+@pytest.fixture(scope="module")
+def contexts():
+    ctx = {}
+    yield ctx
+    for c in ctx.values():
+        c.close()
+
+
+def get_ctx(contexts, name):
+    if name not in contexts:
+        contexts[name] = PROBS[name].context()
+    return contexts[name]
+
+
+@pytest.mark.parametrize("name", list(PROBS))
+@pytest.mark.parametrize("op", OPS, ids=OP_NAMES)
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "fp16"])
+def test_operator_parity(contexts, name, op, prec):
+    P = PROBS[name]
+    print(f"[ops] {name} {OP_NAMES[op]} prec={prec}", flush=True)
+    ctx = get_ctx(contexts, name)
+    psi = P.b
+    got = ctx.apply(op, psi, prec=prec)
+    exp = oracle_op(P, op, psi)
+    tol = TOL[prec]
+    assert rel(got, exp) <= tol, (rel(got, exp), tol)
+    assert max_rel(got, exp) <= 4 * tol
+    if prec == 0:
+        # the parity a block operator does not touch is exactly zero
+        import paper_1101_0423_amd as dwf
+        zero_par = {dwf.OP_HOP_EO: 1, dwf.OP_HOP_OE: 0, dwf.OP_C: 0, dwf.OP_CDAG: 0, dwf.OP_CCDAG: 0}.get(op)
+        if zero_par is not None:
+            assert np.all(on_parity(got, P.dims, zero_par) == 0)
+
+
+def test_multi_rhs_apply_equals_single(contexts):
+    import paper_1101_0423_amd as dwf
+    P = PROBS["ragged"]
+    ctx = get_ctx(contexts, "ragged")
+    bs = inp.gaussian_spinor(P.dims, P.ns, seed=99, nrhs=3)
+    for op in (dwf.OP_C, dwf.OP_CDAG, dwf.OP_D):
+        for prec in (0, 1):
+            many = ctx.apply(op, bs, prec=prec)
+            for k in range(3):
+                one = ctx.apply(op, bs[k], prec=prec)
+                assert np.array_equal(many[k], one)
+
+
+def test_gamma5_hermiticity_on_gpu(contexts):
+    import paper_1101_0423_amd as dwf
+    P = PROBS["odwf8"]
+    ctx = get_ctx(contexts, "odwf8")
+    phi = inp.gaussian_spinor(P.dims, P.ns, seed=5)
+    psi = inp.gaussian_spinor(P.dims, P.ns, seed=6)
+    g5 = np.ones(24)
+    g5[12:] = -1
+    lhs = np.vdot(inp.host_to_complex(phi), inp.host_to_complex(g5 * ctx.apply(dwf.OP_DW, g5 * psi)))
+    rhs = np.vdot(inp.host_to_complex(ctx.apply(dwf.OP_DW, phi)), inp.host_to_complex(psi))
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+    # C and C^dag are adjoints on odd-supported vectors
+    po, so = on_parity(phi, P.dims, 1), on_parity(psi, P.dims, 1)
+    a = np.vdot(inp.host_to_complex(po), inp.host_to_complex(ctx.apply(dwf.OP_C, so)))
+    b = np.vdot(inp.host_to_complex(ctx.apply(dwf.OP_CDAG, po)), inp.host_to_complex(so))
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_full_size_operator_parity():
+    """16^3x32, Ns = 16, the configuration of the primary solve: C, C^dag and D
+    in FP64 and FP32 against the oracle over the whole lattice."""
+    import paper_1101_0423_amd as dwf
+    P = Problem.workload("odwf_16x16x16x32_ns16")
+    ctx = P.context()
+    try:
+        for op in (dwf.OP_C, dwf.OP_CDAG, dwf.OP_D):
+            print(f"[ops] full-size {OP_NAMES[op]}", flush=True)
+            exp = oracle_op(P, op, P.b)
+            for prec in (0, 1):
+                got = ctx.apply(op, P.b, prec=prec)
+                assert rel(got, exp) <= TOL[prec], (op, prec, rel(got, exp))
+                assert max_rel(got, exp) <= 4 * TOL[prec]
+    finally:
+        ctx.close()

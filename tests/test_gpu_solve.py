@@ -1,0 +1,182 @@
+"""GPU solve parity: every solve reaches ||b - D x|| / ||b|| <= 1e-10, measured
+with the oracle's FP64 operator on the GPU's x, and lies within 1e-8
+(relative, norm-wise) of the oracle's own solution solved to 1e-12.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import dwf_inputs as inp
+import oracle
+from _util import Problem, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL_RES = 1e-10
+TOL_FWD = 1e-8
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def check(P, x, xo=None):
+    res = oracle.true_residual(*P.oargs(), P.b, x, bct=P.bct)
+    assert res <= TOL_RES, res
+    if xo is not None:
+        err = rel(x, xo)
+        assert err <= TOL_FWD, err
+    return res
+
+
+_ORACLE = {}
+
+
+def oracle_solution(P, key):
+    if key not in _ORACLE:
+        x, info = oracle.solve(*P.oargs(), P.b, tol=1e-12, bct=P.bct)
+        assert info["converged"]
+        _ORACLE[key] = x
+    return _ORACLE[key]
+
+
+SMALL = Problem.workload("shamir_4x4x4x4_ns8")
+_rng = np.random.default_rng(91)
+RAGGED = Problem((4, 6, 2, 8), 5, 1.6, 0.1, _rng.uniform(0.2, 1.4, 5), _rng.uniform(0.5, 1.5, 5), 0.5, 41, 42,
+                 antiperiodic=True)
+ODWF8 = Problem((8, 8, 8, 8), 16, 1.8, 0.05, *(2 * [_rng.uniform(0.5, 1.5, 16)]), 0.5, 43, 44)
+
+
+@pytest.fixture(scope="module")
+def small_ctx():
+    c = SMALL.context()
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("prec,reliable", [(0, 1), (1, 1), (1, 0), (2, 1), (2, 0)],
+                         ids=["fp64", "fp32-ru", "fp32-dc", "fp16-ru", "fp16-dc"])
+def test_small_solve(small_ctx, prec, reliable):
+    import paper_1101_0423_amd as dwf
+    print(f"[solve] 4^4x8 prec={prec} reliable={reliable}", flush=True)
+    x, st, rc = small_ctx.solve(SMALL.b, inner_prec=prec, reliable=reliable)
+    assert rc == dwf.DWF_OK, st
+    assert st[0]["true_residual"] <= TOL_RES
+    check(SMALL, x, oracle_solution(SMALL, "small"))
+    if prec == 0:
+        assert st[0]["restarts"] <= 3
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_ragged_general_weights(prec):
+    import paper_1101_0423_amd as dwf
+    print(f"[solve] ragged prec={prec}", flush=True)
+    c = RAGGED.context()
+    try:
+        x, st, rc = c.solve(RAGGED.b, inner_prec=prec)
+        assert rc == dwf.DWF_OK, st
+        check(RAGGED, x, oracle_solution(RAGGED, "ragged"))
+    finally:
+        c.close()
+
+
+def test_odwf_ns16_fp32_and_12_real_links():
+    import paper_1101_0423_amd as dwf
+    print("[solve] 8^4x16 odwf", flush=True)
+    c = ODWF8.context()
+    try:
+        xo = oracle_solution(ODWF8, "odwf8")
+        for lc in (0, 1):
+            x, st, rc = c.solve(ODWF8.b, inner_prec=dwf.PREC_FP32, link_compress=lc)
+            assert rc == dwf.DWF_OK, st
+            check(ODWF8, x, xo)
+    finally:
+        c.close()
+
+
+def test_graph_and_plain_launches_agree(small_ctx):
+    x1, s1, _ = small_ctx.solve(SMALL.b, inner_prec=1, use_graph=1)
+    x2, s2, _ = small_ctx.solve(SMALL.b, inner_prec=1, use_graph=0)
+    assert s1[0]["iters"] == s2[0]["iters"]
+    assert np.array_equal(x1, x2)
+
+
+def test_batched_equals_single(small_ctx):
+    import paper_1101_0423_amd as dwf
+    bs = inp.gaussian_spinor(SMALL.dims, SMALL.ns, seed=123, nrhs=3)
+    xb, sb, rc = small_ctx.solve(bs, inner_prec=1)
+    assert rc == dwf.DWF_OK
+    for k in range(3):
+        x1, s1, rc1 = small_ctx.solve(bs[k], inner_prec=1)
+        assert rc1 == dwf.DWF_OK
+        assert rel(xb[k], x1) <= 1e-12
+        P = Problem.workload("shamir_4x4x4x4_ns8")
+        P.b = bs[k]
+        check(P, xb[k])
+
+
+def test_forced_fallback_to_defect_correction(small_ctx):
+    import paper_1101_0423_amd as dwf
+    x, st, rc = small_ctx.solve(SMALL.b, inner_prec=1, reliable=1, debug_stall_after=1, eps_inner=1e-3)
+    assert rc == dwf.DWF_OK
+    assert st[0]["fallback"] == 1
+    check(SMALL, x, oracle_solution(SMALL, "small"))
+
+
+def test_iteration_cap_reports_noconv(small_ctx):
+    import paper_1101_0423_amd as dwf
+    x, st, rc = small_ctx.solve(SMALL.b, inner_prec=1, maxiter=10)
+    assert rc == dwf.DWF_ENOCONV
+    assert st[0]["status"] == dwf.DWF_ENOCONV
+    assert st[0]["true_residual"] > TOL_RES
+
+
+def test_initial_guess_resumes(small_ctx):
+    import paper_1101_0423_amd as dwf
+    xo = oracle_solution(SMALL, "small")
+    pert = xo + 1e-6 * inp.gaussian_spinor(SMALL.dims, SMALL.ns, seed=5)
+    x0, s0, _ = small_ctx.solve(SMALL.b, inner_prec=1)
+    x, st, rc = small_ctx.solve(SMALL.b, x0=pert, inner_prec=1)
+    assert rc == dwf.DWF_OK
+    assert st[0]["iters"] < s0[0]["iters"]
+    check(SMALL, x, xo)
+
+
+def test_zero_rhs(small_ctx):
+    import paper_1101_0423_amd as dwf
+    x, st, rc = small_ctx.solve(np.zeros_like(SMALL.b), inner_prec=1)
+    assert rc == dwf.DWF_OK
+    assert np.all(x == 0)
+
+
+def _golden(name):
+    path = os.path.join(HERE, "golden", f"{name}_oracle_samples.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name,prec,lc", [("odwf_16x16x16x32_ns16", 1, 0), ("odwf_16x16x16x32_ns16", 2, 1)],
+                         ids=["fp32", "fp16-12real"])
+def test_full_size_solve(name, prec, lc):
+    """The primary workload (16^3x32, Ns = 16) in the launch configuration of
+    the benchmark: true residual with the oracle's operator over the whole
+    lattice, forward error on the oracle's stored samples."""
+    import paper_1101_0423_amd as dwf
+    print(f"[solve] full size {name} prec={prec}", flush=True)
+    P = Problem.workload(name)
+    c = P.context()
+    try:
+        x, st, rc = c.solve(P.b, inner_prec=prec, link_compress=lc)
+        print("stats", st[0], flush=True)
+        assert rc == dwf.DWF_OK, st
+        check(P, x)
+        g = _golden(name)
+        if g is not None:
+            got = x.ravel()[np.asarray(g["indices"])]
+            exp = np.asarray(g["values"])
+            # forward error measured on the sampled entries, relative to |x|
+            err = np.linalg.norm(got - exp) / (np.linalg.norm(exp))
+            assert err <= TOL_FWD, err
+    finally:
+        c.close()
