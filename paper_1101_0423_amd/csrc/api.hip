@@ -90,122 +90,6 @@ int Workspace::alloc_state(int n) {
     return DWF_OK;
 }
 
-// ---------------------------------------------------------------------------
-// fifth-dimension tables, Eqs. (3)-(4), (7)-(9)
-// ---------------------------------------------------------------------------
-
-// Solve (diag(a) + diag(b) L) w = z with L = L_+ (ch = 0) or L_- (ch = 1),
-// L_+ w_s = w_{s-1} (s >= 1), L_+ w_0 = -kappa w_{Ns-1}, L_- = L_+^T.  The
-// cyclic bidiagonal system is solved in O(Ns): every w_s is affine in w_0,
-// and the corner equation fixes w_0.  Returns false if singular.
-static bool cyc_solve(int N, const double* a, const double* b, double kappa, int ch, const double* z, double* w) {
-    std::vector<double> A(N), B(N), Z(N), al(N), be(N);
-    for (int s = 0; s < N; ++s) {
-        int k = ch ? N - 1 - s : s;  // L_- is L_+ with s reversed
-        A[s] = a[k];
-        B[s] = b[k];
-        Z[s] = z[k];
-    }
-    al[0] = 0;
-    be[0] = 1;
-    for (int s = 1; s < N; ++s) {
-        if (A[s] == 0) return false;
-        al[s] = (Z[s] - B[s] * al[s - 1]) / A[s];
-        be[s] = -B[s] * be[s - 1] / A[s];
-    }
-    double den = A[0] - kappa * B[0] * be[N - 1];
-    double scale = fabs(A[0]) + fabs(kappa * B[0] * be[N - 1]);
-    if (!(fabs(den) > 1e-13 * scale)) return false;
-    double w0 = (Z[0] + kappa * B[0] * al[N - 1]) / den;
-    for (int s = 0; s < N; ++s) {
-        int k = ch ? N - 1 - s : s;
-        w[k] = al[s] + be[s] * w0;
-    }
-    return true;
-}
-
-bool build_tables(int N, double m0, double mq, const double* sigma, const double* omega, std::vector<double>& out,
-                  std::string& why) {
-    const double kappa = mq / (2.0 * m0);
-    const size_t blk = (size_t)2 * N * N;
-    out.assign(blk * TB_COUNT, 0.0);
-    std::vector<double> a(N), b(N), one(N, 1.0), c(N), col(N), e(N), sw(N);
-    for (int s = 0; s < N; ++s) {
-        c[s] = sigma[s] / omega[s];
-        sw[s] = sqrt(omega[s]);
-    }
-    for (int ch = 0; ch < 2; ++ch) {
-        auto T = [&](int t, int s, int u) -> double& { return out[t * blk + (size_t)ch * N * N + (size_t)s * N + u]; };
-        // L of this chirality
-        std::vector<double> L((size_t)N * N, 0.0);
-        for (int s = 1; s < N; ++s) L[(size_t)s * N + s - 1] = 1.0;
-        L[N - 1] += -kappa;
-        if (ch) {
-            std::vector<double> Lt((size_t)N * N);
-            for (int s = 0; s < N; ++s)
-                for (int u = 0; u < N; ++u) Lt[(size_t)s * N + u] = L[(size_t)u * N + s];
-            L.swap(Lt);
-        }
-        // (1 + cL) must be invertible (Eq. (7))
-        for (int s = 0; s < N; ++s) e[s] = s == 0;
-        if (!cyc_solve(N, one.data(), c.data(), kappa, ch, e.data(), col.data())) {
-            why = "1 + cL is singular for these weights and mass";
-            return false;
-        }
-        // X = (d - m0) omega (1 + cL) + (1 - L) = a + b L, Y = omega + sigma L
-        for (int s = 0; s < N; ++s) {
-            a[s] = (4.0 - m0) * omega[s] + 1.0;
-            b[s] = (4.0 - m0) * sigma[s] - 1.0;
-        }
-        std::vector<double> Xi((size_t)N * N), Yi((size_t)N * N);
-        for (int u = 0; u < N; ++u) {
-            for (int s = 0; s < N; ++s) e[s] = s == u;
-            if (!cyc_solve(N, a.data(), b.data(), kappa, ch, e.data(), col.data())) {
-                why = "X of Eq. (7) is singular for these weights and mass";
-                return false;
-            }
-            for (int s = 0; s < N; ++s) Xi[(size_t)s * N + u] = col[s];
-            if (!cyc_solve(N, omega, sigma, kappa, ch, e.data(), col.data())) {
-                why = "Y of Eq. (7) is singular for these weights and mass";
-                return false;
-            }
-            for (int s = 0; s < N; ++s) Yi[(size_t)s * N + u] = col[s];
-        }
-        for (int s = 0; s < N; ++s)
-            for (int u = 0; u < N; ++u) {
-                double id = s == u;
-                double Lsu = L[(size_t)s * N + u];
-                T(TB_X, s, u) = a[s] * id + b[s] * Lsu;
-                T(TB_Y, s, u) = omega[s] * id + sigma[s] * Lsu;
-                T(TB_1MLT, u, s) = id - Lsu;
-                T(TB_G5, s, u) = ch ? -id : id;
-            }
-        // M5 = sqrt(w)^-1 Y X^-1 sqrt(w)   (Eq. (8))
-        for (int s = 0; s < N; ++s)
-            for (int u = 0; u < N; ++u) {
-                double acc = 0;
-                for (int k = 0; k < N; ++k) acc += T(TB_Y, s, k) * Xi[(size_t)k * N + u];
-                T(TB_M5, s, u) = acc * sw[u] / sw[s];
-            }
-        for (int s = 0; s < N; ++s)
-            for (int u = 0; u < N; ++u) {
-                const double m = T(TB_M5, s, u);
-                T(TB_M5T, u, s) = m;
-                T(TB_M5TG5, u, s) = ch ? -m : m;
-                T(TB_S1, s, u) = m / sw[u];                       // S1 = M5 sqrt(w)^-1
-                T(TB_S2, s, u) = Yi[(size_t)s * N + u] * sw[u];   // S2 = Y^-1 sqrt(w)
-                T(TB_S2INV, s, u) = T(TB_Y, s, u) / sw[s];        // S2^-1 = sqrt(w)^-1 Y
-                T(TB_YTG5, u, s) = ch ? -T(TB_Y, s, u) : T(TB_Y, s, u);
-            }
-    }
-    for (double v : out)
-        if (!std::isfinite(v)) {
-            why = "non-finite fifth-dimension table";
-            return false;
-        }
-    return true;
-}
-
 }  // namespace dwf
 
 using namespace dwf;

@@ -13,6 +13,7 @@
 
 #include "../../include/dwf.h"
 #include "dwf_device.h"
+#include "fifth_dim.h"
 
 namespace dwf {
 
@@ -51,34 +52,16 @@ struct DevBuf {
 // Link formats held per parity.
 enum LinkFmt { LINK_D18 = 0, LINK_S18 = 1, LINK_S12 = 2, LINK_H12 = 3, LINK_NFMT = 4 };
 
-// Fifth-dimension tables: [2 chiralities][Ns][Ns] each.
-enum Table {
-    TB_M5 = 0,    // M5 of Eq. (8)
-    TB_M5T,       // M5^T
-    TB_M5TG5,     // M5^T gamma_5 (gamma_5 folded into the chirality blocks)
-    TB_S1,        // S1 = M5 sqrt(omega)^-1, Eq. (9)
-    TB_S2,        // S2 = Y^-1 sqrt(omega), Eq. (9)
-    TB_S2INV,     // S2^-1 = sqrt(omega)^-1 Y
-    TB_X,         // X of Eq. (7)
-    TB_Y,         // Y of Eq. (7)
-    TB_YTG5,      // Y^T gamma_5
-    TB_1MLT,      // (1 - L)^T
-    TB_G5,        // gamma_5
-    TB_COUNT
-};
-
 // Tables of one quark mass (the mass enters through L's corner).
 struct TableSet {
     double mq = 0;
-    std::vector<double> host;  // TB_COUNT * 2 * Ns * Ns
+    std::vector<double> host;  // tables_size(Ns) reals (fifth_dim.h)
     DevBuf d64, d32;
-    const double* t64(int t, int Ns) const { return d64.as<double>() + (size_t)t * 2 * Ns * Ns; }
-    const float* t32(int t, int Ns) const { return d32.as<float>() + (size_t)t * 2 * Ns * Ns; }
+    const double* t64(int t, int Ns) const { return d64.as<double>() + dense_table_offset(Ns, t); }
+    const float* t32(int t, int Ns) const { return d32.as<float>() + dense_table_offset(Ns, t); }
+    const double* s64(int st, int Ns) const { return d64.as<double>() + struct_table_offset(Ns, st); }
+    const float* s32(int st, int Ns) const { return d32.as<float>() + struct_table_offset(Ns, st); }
 };
-
-// Build all tables on the host; false if (1 + cL) or X is singular.
-bool build_tables(int Ns, double m0, double mq, const double* sigma, const double* omega,
-                  std::vector<double>& out, std::string& why);
 
 // A half field (one parity) of nrhs right-hand sides in a given precision.
 struct HalfField {
@@ -152,19 +135,19 @@ namespace dwf {
 
 inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
-template <class Real, class F, class LF, bool HOP, bool MIX, class Pro, class Epi>
+template <class Real, class F, class LF, bool HOP, int MIXM, class Pro, class Epi>
 hipError_t launch_dwf(const Geom& g, const F& in, const LF& links, const Real* table, const Pro& pro,
                       const Epi& epi, KOpt o, hipStream_t st) {
     int T = round_up(g.G * g.Ns, 64);
-    size_t sm = kernel_smem<Real>(g.G, g.Ns, HOP, MIX);
+    size_t sm = kernel_smem<Real>(g.G, g.Ns, HOP, MIXM != MIX_NONE);
     if (g.Ns <= 8)
-        hipLaunchKernelGGL((k_dwf<Real, F, LF, 8, HOP, MIX, Pro, Epi>), dim3(g.nblocks), dim3(T), sm, st, g, in,
+        hipLaunchKernelGGL((k_dwf<Real, F, LF, 8, HOP, MIXM, Pro, Epi>), dim3(g.nblocks), dim3(T), sm, st, g, in,
                            links, table, pro, epi, o);
     else if (g.Ns <= 16)
-        hipLaunchKernelGGL((k_dwf<Real, F, LF, 16, HOP, MIX, Pro, Epi>), dim3(g.nblocks), dim3(T), sm, st, g, in,
+        hipLaunchKernelGGL((k_dwf<Real, F, LF, 16, HOP, MIXM, Pro, Epi>), dim3(g.nblocks), dim3(T), sm, st, g, in,
                            links, table, pro, epi, o);
     else
-        hipLaunchKernelGGL((k_dwf<Real, F, LF, 32, HOP, MIX, Pro, Epi>), dim3(g.nblocks), dim3(T), sm, st, g, in,
+        hipLaunchKernelGGL((k_dwf<Real, F, LF, 32, HOP, MIXM, Pro, Epi>), dim3(g.nblocks), dim3(T), sm, st, g, in,
                            links, table, pro, epi, o);
     return hipGetLastError();
 }

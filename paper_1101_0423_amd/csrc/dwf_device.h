@@ -417,10 +417,112 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------
+// fifth-dimension matrix on one column (one 4D site, one real spinor
+// component, all Ns slices), values h[] at base[t * 24] in LDS.
+//   MIX_DENSE: out_s = sum_t T[s][t] h_t (any Ns x Ns table)
+//   MIX_SA / MIX_AS: M5 / M5^T (and M5^T gamma_5) through their O(Ns)
+//   recurrences, coefficient arrays F, G, B, P, Q, O of the chirality block
+//   (built on the host, see fifth_dim.h), s reversed where the shift runs
+//   backwards.  All coefficients are wave-uniform (scalar loads).
+// ---------------------------------------------------------------------------
+
+enum MixMode { MIX_NONE = 0, MIX_DENSE = 1, MIX_SA = 2, MIX_AS = 3 };
+
+template <class Real, int NSMAX>
+__device__ __forceinline__ void mix_dense(Real* base, const Real* __restrict__ M, int Ns) {
+    Real h[NSMAX];
+#pragma unroll
+    for (int t = 0; t < NSMAX; ++t)
+        if (t < Ns) h[t] = base[t * 24];
+#pragma unroll
+    for (int ss = 0; ss < NSMAX; ++ss) {
+        if (ss < Ns) {
+            Real acc = 0;
+#pragma unroll
+            for (int t = 0; t < NSMAX; ++t)
+                if (t < Ns) acc += M[ss * Ns + t] * h[t];
+            base[ss * 24] = acc;
+        }
+    }
+}
+
+template <class Real, int NSMAX, int MODE>
+__device__ __forceinline__ void mix_structured(Real* base, const Real* __restrict__ C, int N, bool rev) {
+    // column in recurrence order
+    Real h[NSMAX];
+#pragma unroll
+    for (int k = 0; k < NSMAX; ++k)
+        if (k < N) h[k] = base[(rev ? N - 1 - k : k) * 24];
+    const Real* F = C;
+    const Real* G = C + N;
+    const Real* B = C + 2 * N;
+    const Real* P = C + 3 * N;
+    const Real* Q = C + 4 * N;
+    const Real* O = C + 5 * N;
+    Real o[NSMAX];
+    if constexpr (MODE == MIX_SA) {
+        // w = X^-1 sqrt(w) h : alpha sweep, corner equation for w_0
+        Real al[NSMAX];
+        al[0] = 0;
+        Real last = 0;
+#pragma unroll
+        for (int k = 1; k < NSMAX; ++k)
+            if (k < N) {
+                al[k] = F[k] * h[k] - G[k] * al[k - 1];
+                last = al[k];
+            }
+        const Real w0 = F[0] * h[0] + G[0] * last;
+        Real w[NSMAX];
+        w[0] = w0;
+        Real wl = w0;
+#pragma unroll
+        for (int k = 1; k < NSMAX; ++k)
+            if (k < N) {
+                w[k] = al[k] + B[k] * w0;
+                wl = w[k];
+            }
+        // out = sqrt(w)^-1 Y w
+        o[0] = P[0] * w0 + Q[0] * wl;
+#pragma unroll
+        for (int k = 1; k < NSMAX; ++k)
+            if (k < N) o[k] = P[k] * w[k] + Q[k] * w[k - 1];
+    } else {
+        // g = Y^T sqrt(w)^-1 h
+        Real hl = 0;
+#pragma unroll
+        for (int k = 0; k < NSMAX; ++k)
+            if (k == N - 1) hl = h[k];
+        Real gg[NSMAX];
+        gg[0] = P[0] * h[0] + Q[0] * hl;
+#pragma unroll
+        for (int k = 1; k < NSMAX; ++k)
+            if (k < N) gg[k] = P[k] * h[k] + Q[k] * h[k - 1];
+        // w = X^-T g, out = sqrt(w) w
+        Real al[NSMAX];
+        al[0] = 0;
+        Real last = 0;
+#pragma unroll
+        for (int k = 1; k < NSMAX; ++k)
+            if (k < N) {
+                al[k] = F[k] * gg[k] - G[k] * al[k - 1];
+                last = al[k];
+            }
+        const Real w0 = F[0] * gg[0] + G[0] * last;
+#pragma unroll
+        for (int k = 0; k < NSMAX; ++k)
+            if (k < N) o[k] = O[k] * al[k] + B[k] * w0;
+    }
+#pragma unroll
+    for (int k = 0; k < NSMAX; ++k)
+        if (k < N) base[(rev ? N - 1 - k : k) * 24] = o[k];
+}
+
+// ---------------------------------------------------------------------------
 // the fused kernel
 //   phase 1: v = hop(in) on every (site, s) lane     [HOP]
 //            v = prologue(site, s)                   [!HOP]
-//   phase 2: v_s = sum_t T[ch][s][t] v_t per 4D site  [MIX]  (LDS transpose)
+//   phase 2: the fifth-dimension matrix per 4D site  [MIXM != MIX_NONE]
+//            (LDS transpose: lanes switch from (site, s) to (site, column))
 //   phase 3: epilogue(site, s, v) -> norm contribution, block-reduced
 // One workgroup covers G consecutive 4D half sites x all Ns slices, lane
 // (sl, s) = (tid / Ns, tid % Ns), so the SoA loads of consecutive lanes are
@@ -450,9 +552,10 @@ __host__ __device__ inline size_t kernel_smem(int G, int Ns, bool hop, bool mix)
     return b;
 }
 
-template <class Real, class F, class LF, int NSMAX, bool HOP, bool MIX, class Pro, class Epi>
+template <class Real, class F, class LF, int NSMAX, bool HOP, int MIXM, class Pro, class Epi>
 __global__ void __launch_bounds__(256)
 k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, KOpt o) {
+    constexpr bool MIX = MIXM != MIX_NONE;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int LS = LdsLink<Real>::STR;
     const int Ns = g.Ns;
@@ -526,21 +629,11 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
                 if (col < ncol) {
                     const int cs = col / 12, cc = col - cs * 12;
                     Real* base = hb + cs * hs + ch * 12 + cc;
-                    const Real* M = tb + ch * Ns * Ns;
-                    Real h[NSMAX];
-#pragma unroll
-                    for (int t = 0; t < NSMAX; ++t)
-                        if (t < Ns) h[t] = base[t * 24];
-#pragma unroll
-                    for (int ss = 0; ss < NSMAX; ++ss) {
-                        if (ss < Ns) {
-                            Real acc = 0;
-#pragma unroll
-                            for (int t = 0; t < NSMAX; ++t)
-                                if (t < Ns) acc += M[ss * Ns + t] * h[t];
-                            base[ss * 24] = acc;
-                        }
-                    }
+                    if constexpr (MIXM == MIX_DENSE)
+                        mix_dense<Real, NSMAX>(base, tb + ch * Ns * Ns, Ns);
+                    else  // M5: reversed for L_-; M5^T: reversed for L_+^T = L_-
+                        mix_structured<Real, NSMAX, MIXM>(base, tb + ch * 6 * Ns, Ns,
+                                                          (ch == 1) != (MIXM == MIX_AS));
                 }
             }
             __syncthreads();

@@ -21,6 +21,12 @@ template <>
 const double* tab<double>(const TableSet* ts, int t, int Ns) { return ts->t64(t, Ns); }
 template <>
 const float* tab<float>(const TableSet* ts, int t, int Ns) { return ts->t32(t, Ns); }
+template <class Real>
+const Real* stab(const TableSet* ts, int t, int Ns);
+template <>
+const double* stab<double>(const TableSet* ts, int t, int Ns) { return ts->s64(t, Ns); }
+template <>
+const float* stab<float>(const TableSet* ts, int t, int Ns) { return ts->s32(t, Ns); }
 
 namespace {
 
@@ -38,24 +44,37 @@ struct Applier {
     Geom geom(int par) const { return c->geom(par, sizeof(Real) == 8); }
     F f(int i) const { return fld<F>(w->f(i)); }
     const Real* t(int which) const { return tab<Real>(ts, which, c->Ns); }
+    const Real* ts_(int which) const { return stab<Real>(ts, which, c->Ns); }
 
     // out(par) = epi( hop(in) )
     template <class Epi>
     hipError_t hop(int par, int in, const Epi& epi) {
-        return launch_dwf<Real, F, LF, true, false, ProLoad<F>, Epi>(geom(par), f(in), lk[par], nullptr,
-                                                                     ProLoad<F>{f(in)}, epi, o, s);
+        return launch_dwf<Real, F, LF, true, MIX_NONE, ProLoad<F>, Epi>(geom(par), f(in), lk[par], nullptr,
+                                                                         ProLoad<F>{f(in)}, epi, o, s);
     }
-    // out(par) = epi( T hop(in) )
+    // out(par) = epi( M hop(in) ), M = M5 (st = ST_M5) or M5^T (st = ST_M5T) by recurrence
     template <class Epi>
-    hipError_t hopmix(int par, int in, int table, const Epi& epi) {
-        return launch_dwf<Real, F, LF, true, true, ProLoad<F>, Epi>(geom(par), f(in), lk[par], t(table),
-                                                                    ProLoad<F>{f(in)}, epi, o, s);
+    hipError_t hopmix(int par, int in, int st, const Epi& epi) {
+        if (st == ST_M5)
+            return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, Epi>(geom(par), f(in), lk[par], ts_(st),
+                                                                          ProLoad<F>{f(in)}, epi, o, s);
+        return launch_dwf<Real, F, LF, true, MIX_AS, ProLoad<F>, Epi>(geom(par), f(in), lk[par], ts_(st),
+                                                                      ProLoad<F>{f(in)}, epi, o, s);
     }
-    // out(par) = epi( T in )
+    // out(par) = epi( T in ) with a dense table
     template <class Epi>
     hipError_t local(int par, int in, int table, const Epi& epi) {
-        return launch_dwf<Real, F, LF, false, true, ProLoad<F>, Epi>(geom(par), f(in), lk[par], t(table),
-                                                                     ProLoad<F>{f(in)}, epi, o, s);
+        return launch_dwf<Real, F, LF, false, MIX_DENSE, ProLoad<F>, Epi>(geom(par), f(in), lk[par], t(table),
+                                                                          ProLoad<F>{f(in)}, epi, o, s);
+    }
+    // out(par) = epi( M in ) by recurrence (M5, M5^T or M5^T gamma_5)
+    template <class Epi>
+    hipError_t local_st(int par, int in, int st, const Epi& epi) {
+        if (st == ST_M5)
+            return launch_dwf<Real, F, LF, false, MIX_SA, ProLoad<F>, Epi>(geom(par), f(in), lk[par], ts_(st),
+                                                                           ProLoad<F>{f(in)}, epi, o, s);
+        return launch_dwf<Real, F, LF, false, MIX_AS, ProLoad<F>, Epi>(geom(par), f(in), lk[par], ts_(st),
+                                                                       ProLoad<F>{f(in)}, epi, o, s);
     }
     EpiStore<F> store(int i) const { return EpiStore<F>{f(i)}; }
     EpiLin<F, F, false, false> lin(int a, int out, double ca, double cv) const {
@@ -87,25 +106,25 @@ struct Applier {
                 break;
             case DWF_OP_M5:
             case DWF_OP_M5T: {
-                int tb = op == DWF_OP_M5 ? TB_M5 : TB_M5T;
-                CK(local(0, IN_E, tb, store(OUT_E)));
-                CK(local(1, IN_O, tb, store(OUT_O)));
+                int st = op == DWF_OP_M5 ? ST_M5 : ST_M5T;
+                CK(local_st(0, IN_E, st, store(OUT_E)));
+                CK(local_st(1, IN_O, st, store(OUT_O)));
                 break;
             }
             case DWF_OP_C:
-                CK(hopmix(0, IN_O, TB_M5, store(T_E)));
-                CK(hopmix(1, T_E, TB_M5, lin(IN_O, OUT_O, 1.0, -1.0)));
+                CK(hopmix(0, IN_O, ST_M5, store(T_E)));
+                CK(hopmix(1, T_E, ST_M5, lin(IN_O, OUT_O, 1.0, -1.0)));
                 CK(zero(OUT_E));
                 break;
             case DWF_OP_CDAG:
             case DWF_OP_CCDAG: {
                 int dst = op == DWF_OP_CDAG ? OUT_O : T2_O;
-                CK(local(1, IN_O, TB_M5TG5, store(T_O)));
-                CK(hopmix(0, T_O, TB_M5T, store(T_E)));
+                CK(local_st(1, IN_O, ST_M5TG5, store(T_O)));
+                CK(hopmix(0, T_O, ST_M5T, store(T_E)));
                 CK(hop(1, T_E, EpiLin<F, F, false, true>{f(IN_O), f(dst), 1.0, -1.0}));
                 if (op == DWF_OP_CCDAG) {
-                    CK(hopmix(0, T2_O, TB_M5, store(T_E)));
-                    CK(hopmix(1, T_E, TB_M5, lin(T2_O, OUT_O, 1.0, -1.0)));
+                    CK(hopmix(0, T2_O, ST_M5, store(T_E)));
+                    CK(hopmix(1, T_E, ST_M5, lin(T2_O, OUT_O, 1.0, -1.0)));
                 }
                 CK(zero(OUT_E));
                 break;

@@ -36,6 +36,8 @@ template <class F>
 F fld(const HalfField& h);
 template <class Real>
 const Real* tab(const TableSet* ts, int t, int Ns);
+template <class Real>
+const Real* stab(const TableSet* ts, int t, int Ns);
 
 double flops_per_iter(const dwf_ctx* c) {
     return (double)c->V5h * (5280.0 + 192.0 * c->Ns + 288.0);
@@ -81,37 +83,39 @@ struct Solver {
     FY ylo() const { return fld<FY>(w->f(L_Y)); }
     const double* t64(int t) const { return tab<double>(ts, t, c->Ns); }
     const Real* tlo(int t) const { return tab<Real>(ts, t, c->Ns); }
+    const double* s64(int t) const { return stab<double>(ts, t, c->Ns); }
+    const Real* slo(int t) const { return stab<Real>(ts, t, c->Ns); }
     double* part() const { return partials->as<double>(); }
     KOpt kopt(const int* live, bool red) const { return KOpt{live, red ? part() : nullptr, nrhs, 0}; }
 
     // ---------------- FP64 pieces ----------------
     hipError_t local64(int par, int in, int table, int out) {
-        return launch_dwf<double, FD, LinkD18, false, true, ProLoad<FD>, EpiStore<FD>>(
+        return launch_dwf<double, FD, LinkD18, false, MIX_DENSE, ProLoad<FD>, EpiStore<FD>>(
             g64(par), d(in), lk64[par], t64(table), ProLoad<FD>{d(in)}, EpiStore<FD>{d(out)}, kopt(nullptr, false), s);
     }
     hipError_t norm64(int par, int in) {
-        return launch_dwf<double, FD, LinkD18, false, false, ProLoad<FD>, EpiNorm>(
+        return launch_dwf<double, FD, LinkD18, false, MIX_NONE, ProLoad<FD>, EpiNorm>(
             g64(par), d(in), lk64[par], nullptr, ProLoad<FD>{d(in)}, EpiNorm{}, kopt(nullptr, true), s);
     }
     // out = a - M5 D^{par,1-par} in
     hipError_t xmy_m5hop64(int par, int in, int a, int out, bool red) {
         if (red)
-            return launch_dwf<double, FD, LinkD18, true, true, ProLoad<FD>, EpiLin<FD, FD, true, false>>(
-                g64(par), d(in), lk64[par], t64(TB_M5), ProLoad<FD>{d(in)},
+            return launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiLin<FD, FD, true, false>>(
+                g64(par), d(in), lk64[par], s64(ST_M5), ProLoad<FD>{d(in)},
                 EpiLin<FD, FD, true, false>{d(a), d(out), 1.0, -1.0}, kopt(nullptr, true), s);
-        return launch_dwf<double, FD, LinkD18, true, true, ProLoad<FD>, EpiLin<FD, FD, false, false>>(
-            g64(par), d(in), lk64[par], t64(TB_M5), ProLoad<FD>{d(in)},
+        return launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiLin<FD, FD, false, false>>(
+            g64(par), d(in), lk64[par], s64(ST_M5), ProLoad<FD>{d(in)},
             EpiLin<FD, FD, false, false>{d(a), d(out), 1.0, -1.0}, kopt(nullptr, false), s);
     }
     hipError_t fin(int nblocks, int mode) { return launch_finish(part(), nblocks, nrhs, w->st, mode, s); }
 
     // rhat = b'' - C yhat_o  (FP64), r_lo = rhat, y_lo = 0, rr = aux = |rhat|^2
     hipError_t outer_residual() {
-        hipError_t e = launch_dwf<double, FD, LinkD18, true, true, ProLoad<FD>, EpiStore<FD>>(
-            g64(0), d(YH_O), lk64[0], t64(TB_M5), ProLoad<FD>{d(YH_O)}, EpiStore<FD>{d(T64_E)}, kopt(nullptr, false), s);
+        hipError_t e = launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiStore<FD>>(
+            g64(0), d(YH_O), lk64[0], s64(ST_M5), ProLoad<FD>{d(YH_O)}, EpiStore<FD>{d(T64_E)}, kopt(nullptr, false), s);
         if (e != hipSuccess) return e;
-        e = launch_dwf<double, FD, LinkD18, true, true, ProLoad<FD>, EpiOuter<FD, FD, F, FY>>(
-            g64(1), d(T64_E), lk64[1], t64(TB_M5), ProLoad<FD>{d(T64_E)},
+        e = launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiOuter<FD, FD, F, FY>>(
+            g64(1), d(T64_E), lk64[1], s64(ST_M5), ProLoad<FD>{d(T64_E)},
             EpiOuter<FD, FD, F, FY>{d(BPP), d(YH_O), lo(L_R), ylo()}, kopt(nullptr, true), s);
         if (e != hipSuccess) return e;
         return fin(g64(1).nblocks, FIN_OUTER);
@@ -119,27 +123,27 @@ struct Solver {
 
     // ---------------- inner CG kernels ----------------
     hipError_t kE(const int* live, const int* reset) {
-        return launch_dwf<Real, F, LF, false, true, ProCgE<F, F>, EpiStore<F>>(
-            glo(1), lo(L_R), lk[1], tlo(TB_M5TG5), ProCgE<F, F>{lo(L_R), lo(L_P), w->st.beta, reset},
+        return launch_dwf<Real, F, LF, false, MIX_AS, ProCgE<F, F>, EpiStore<F>>(
+            glo(1), lo(L_R), lk[1], slo(ST_M5TG5), ProCgE<F, F>{lo(L_R), lo(L_P), w->st.beta, reset},
             EpiStore<F>{lo(L_T1)}, kopt(live, false), s);
     }
     hipError_t kA() {
-        return launch_dwf<Real, F, LF, true, true, ProLoad<F>, EpiStore<F>>(
-            glo(0), lo(L_T1), lk[0], tlo(TB_M5T), ProLoad<F>{lo(L_T1)}, EpiStore<F>{lo(L_T23)}, kopt(w->st.live, false),
+        return launch_dwf<Real, F, LF, true, MIX_AS, ProLoad<F>, EpiStore<F>>(
+            glo(0), lo(L_T1), lk[0], slo(ST_M5T), ProLoad<F>{lo(L_T1)}, EpiStore<F>{lo(L_T23)}, kopt(w->st.live, false),
             s);
     }
     hipError_t kB() {
-        return launch_dwf<Real, F, LF, true, false, ProLoad<F>, EpiCgB<F, F>>(
+        return launch_dwf<Real, F, LF, true, MIX_NONE, ProLoad<F>, EpiCgB<F, F>>(
             glo(1), lo(L_T23), lk[1], nullptr, ProLoad<F>{lo(L_T23)}, EpiCgB<F, F>{lo(L_P), lo(L_U)},
             kopt(w->st.live, true), s);
     }
     hipError_t kC() {
-        return launch_dwf<Real, F, LF, true, true, ProLoad<F>, EpiStore<F>>(
-            glo(0), lo(L_U), lk[0], tlo(TB_M5), ProLoad<F>{lo(L_U)}, EpiStore<F>{lo(L_T23)}, kopt(w->st.live, false), s);
+        return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiStore<F>>(
+            glo(0), lo(L_U), lk[0], slo(ST_M5), ProLoad<F>{lo(L_U)}, EpiStore<F>{lo(L_T23)}, kopt(w->st.live, false), s);
     }
     hipError_t kD() {
-        return launch_dwf<Real, F, LF, true, true, ProLoad<F>, EpiCgD<F, F, FY>>(
-            glo(1), lo(L_T23), lk[1], tlo(TB_M5), ProLoad<F>{lo(L_T23)},
+        return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiCgD<F, F, FY>>(
+            glo(1), lo(L_T23), lk[1], slo(ST_M5), ProLoad<F>{lo(L_T23)},
             EpiCgD<F, F, FY>{lo(L_U), lo(L_R), ylo(), w->st.alpha}, kopt(w->st.live, true), s);
     }
     hipError_t iteration(bool with_e) {
@@ -494,14 +498,14 @@ int run_solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dw
             // even rows: b_e - X x_e - D^EO (Y x)_o ; X x_e -> YH_O is free? no: keep yhat_o.
             // use BPP for X x_e, then odd rows with X x_o in BPP again.
             CKE(S.local64(0, BP_E, TB_X, BPP));
-            CKE((launch_dwf<double, FD, LinkD18, true, false, ProLoad<FD>, EpiTrueRes<FD, FD>>(
+            CKE((launch_dwf<double, FD, LinkD18, true, MIX_NONE, ProLoad<FD>, EpiTrueRes<FD, FD>>(
                 S.g64(0), S.d(T64_E), S.lk64[0], nullptr, ProLoad<FD>{S.d(T64_E)},
                 EpiTrueRes<FD, FD>{S.d(B_E), S.d(BPP)}, S.kopt(nullptr, true), s)));
             CKE(S.fin(nb64e, FIN_AUX));
             CKR(pull());
             for (int r = 0; r < nrhs; ++r) tr[r] = h_aux[r];
             CKE(S.local64(1, BP_O, TB_X, BPP));
-            CKE((launch_dwf<double, FD, LinkD18, true, false, ProLoad<FD>, EpiTrueRes<FD, FD>>(
+            CKE((launch_dwf<double, FD, LinkD18, true, MIX_NONE, ProLoad<FD>, EpiTrueRes<FD, FD>>(
                 S.g64(1), S.d(YH_E), S.lk64[1], nullptr, ProLoad<FD>{S.d(YH_E)},
                 EpiTrueRes<FD, FD>{S.d(B_O), S.d(BPP)}, S.kopt(nullptr, true), s)));
             CKE(S.fin(nb64o, FIN_AUX));
@@ -591,26 +595,27 @@ int time_kernels(dwf_ctx* c, const dwf_solve_params& p, int nrhs, int launches, 
         switch (k) {
             case 0: return S.kE(nolive, nullptr);
             case 1:
-                return launch_dwf<Real, F, LF, true, true, ProLoad<F>, EpiStore<F>>(
-                    S.glo(0), S.lo(L_T1), S.lk[0], S.tlo(TB_M5T), ProLoad<F>{S.lo(L_T1)}, EpiStore<F>{S.lo(L_T23)},
+                return launch_dwf<Real, F, LF, true, MIX_AS, ProLoad<F>, EpiStore<F>>(
+                    S.glo(0), S.lo(L_T1), S.lk[0], S.slo(ST_M5T), ProLoad<F>{S.lo(L_T1)}, EpiStore<F>{S.lo(L_T23)},
                     S.kopt(nolive, false), s);
             case 2:
-                return launch_dwf<Real, F, LF, true, false, ProLoad<F>, EpiCgB<F, F>>(
+                return launch_dwf<Real, F, LF, true, MIX_NONE, ProLoad<F>, EpiCgB<F, F>>(
                     S.glo(1), S.lo(L_T23), S.lk[1], nullptr, ProLoad<F>{S.lo(L_T23)}, EpiCgB<F, F>{S.lo(L_P), S.lo(L_U)},
                     S.kopt(nolive, true), s);
             case 3:
-                return launch_dwf<Real, F, LF, true, true, ProLoad<F>, EpiStore<F>>(
-                    S.glo(0), S.lo(L_U), S.lk[0], S.tlo(TB_M5), ProLoad<F>{S.lo(L_U)}, EpiStore<F>{S.lo(L_T23)},
+                return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiStore<F>>(
+                    S.glo(0), S.lo(L_U), S.lk[0], S.slo(ST_M5), ProLoad<F>{S.lo(L_U)}, EpiStore<F>{S.lo(L_T23)},
                     S.kopt(nolive, false), s);
             default:
-                return launch_dwf<Real, F, LF, true, true, ProLoad<F>, EpiCgD<F, F, FY>>(
-                    S.glo(1), S.lo(L_T23), S.lk[1], S.tlo(TB_M5), ProLoad<F>{S.lo(L_T23)},
+                return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiCgD<F, F, FY>>(
+                    S.glo(1), S.lo(L_T23), S.lk[1], S.slo(ST_M5), ProLoad<F>{S.lo(L_T23)},
                     EpiCgD<F, F, FY>{S.lo(L_U), S.lo(L_R), S.ylo(), w->st.alpha}, S.kopt(nolive, true), s);
         }
     };
-    hipEvent_t e0, e1;
-    DWF_HIP(hipEventCreate(&e0));
-    DWF_HIP(hipEventCreate(&e1));
+    // one event pair around every launch: the average is the kernels' own
+    // device time, without the dispatch gap between back-to-back launches
+    std::vector<hipEvent_t> ev(2 * (size_t)launches, nullptr);
+    for (auto& e : ev) DWF_HIP(hipEventCreate(&e));
     const double sb = spinor_bytes(p.inner_prec) * (double)c->V5h * nrhs;
     const double yb = (p.inner_prec == DWF_PREC_FP64 ? 192.0 : 96.0) * (double)c->V5h * nrhs;
     const double lb = (double)c->V4h * 8.0 * link_bytes(link_fmt);
@@ -618,21 +623,26 @@ int time_kernels(dwf_ctx* c, const dwf_solve_params& p, int nrhs, int launches, 
     int result = DWF_OK;
     for (int k = 0; k < 5 && result == DWF_OK; ++k) {
         hipError_t e = runk(k);  // warm-up launch
-        if (e == hipSuccess) e = hipEventRecord(e0, s);
-        for (int i = 0; i < launches && e == hipSuccess; ++i) e = runk(k);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float t = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        for (int i = 0; i < launches && e == hipSuccess; ++i) {
+            e = hipEventRecord(ev[2 * i], s);
+            if (e == hipSuccess) e = runk(k);
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], s);
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2 * launches - 1]);
+        double tot = 0;
+        for (int i = 0; i < launches && e == hipSuccess; ++i) {
+            float t = 0;
+            e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+            tot += t;
+        }
         if (e != hipSuccess) {
             result = fail(DWF_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
             break;
         }
-        ms[k] = t / launches;
+        ms[k] = tot / launches;
         bytes[k] = model[k];
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto& e : ev) (void)hipEventDestroy(e);
     return result;
 }
 
