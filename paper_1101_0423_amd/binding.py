@@ -35,7 +35,7 @@ class DwfError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("antiperiodic_t", ctypes.c_int), ("device", ctypes.c_int), ("sites_per_block", ctypes.c_int),
-                ("reserved0", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t)]
+                ("xcd_remap", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t)]
 
 
 class SolveParams(ctypes.Structure):
@@ -147,7 +147,7 @@ class Context:
     """One operator: resident gauge field and fifth-dimension tables (dwf_create)."""
 
     def __init__(self, gauge, dims, ns, m0, mq, sigma, omega, antiperiodic_t=False, device=0,
-                 sites_per_block=0, hbm_budget_bytes=0):
+                 sites_per_block=0, hbm_budget_bytes=0, xcd_remap=0):
         L = lib()
         self._h = ctypes.c_void_p()
         o = Opts()
@@ -155,6 +155,7 @@ class Context:
         o.antiperiodic_t = int(antiperiodic_t)
         o.device = device
         o.sites_per_block = sites_per_block
+        o.xcd_remap = xcd_remap
         o.hbm_budget_bytes = hbm_budget_bytes
         self.gauge = _f64(gauge)
         self.dims = tuple(int(d) for d in dims)

@@ -7,8 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-OBJ = os.path.join(HERE, "_build")
-LIB = os.path.join(HERE, "libdwf.so")
+OBJ = os.environ.get("DWF_OBJ_DIR", os.path.join(HERE, "_build"))
+LIB = os.environ.get("DWF_LIB_OUT", os.path.join(HERE, "libdwf.so"))
 SOURCES = ["api.hip", "layout.hip", "ops.hip", "solver.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -18,7 +18,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
     "-Wno-unused-result",
-]
+] + os.environ.get("DWF_EXTRA_FLAGS", "").split()
 
 
 def _compile(src):

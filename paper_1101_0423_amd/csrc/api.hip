@@ -40,29 +40,29 @@ void DevBuf::release() {
     bytes = 0;
 }
 
-int HalfField::alloc(int prec_, long V5h, int nrhs_) {
+int HalfField::alloc(int prec_, long V5h, int Ns, int nrhs_) {
     prec = prec_;
     nrhs = nrhs_;
-    // pad every component block; the extra 64 elements stagger the blocks
-    // over the HBM channels
-    stride = ((V5h + 255) / 256) * 256 + 64;
+    ns = Ns;
     int nblk = prec == DWF_PREC_FP64 ? 12 : prec == DWF_PREC_FP32 ? 6 : 3;
-    rstride = stride * nblk;
+    // right-hand sides start on 4 KiB boundaries
+    rstride = ((V5h * nblk + 255) / 256) * 256;
     int rc = data.alloc((size_t)rstride * nrhs * 16);
     if (rc) return rc;
     if (prec == DWF_PREC_FP16) {
-        rc = nrm.alloc((size_t)stride * nrhs * sizeof(float));
+        nstride = ((V5h + 1023) / 1024) * 1024;
+        rc = nrm.alloc((size_t)nstride * nrhs * sizeof(float));
         if (rc) return rc;
     }
     return DWF_OK;
 }
 
-int Workspace::alloc(const std::vector<int>& precs, long V5h, int nrhs_) {
+int Workspace::alloc(const std::vector<int>& precs, long V5h, int Ns, int nrhs_) {
     nrhs = nrhs_;
     fields.clear();
     for (int pr : precs) {
         fields.emplace_back(new HalfField);
-        int rc = fields.back()->alloc(pr, V5h, nrhs_);
+        int rc = fields.back()->alloc(pr, V5h, Ns, nrhs_);
         if (rc) return rc;
     }
     return DWF_OK;
@@ -107,7 +107,7 @@ dwf::Geom dwf_ctx::geom(int out_parity, bool fp64) const {
     g.out_parity = out_parity;
     g.antiper = opts.antiperiodic_t ? 1 : 0;
     g.nblocks = (int)((V4h + g.G - 1) / g.G);
-    g.xcd = 1;
+    g.xcd = opts.xcd_remap < 0 ? 0 : 1;
     return g;
 }
 

@@ -63,22 +63,20 @@ struct TableSet {
     const float* s32(int st, int Ns) const { return d32.as<float>() + struct_table_offset(Ns, st); }
 };
 
-// A half field (one parity) of nrhs right-hand sides in a given precision.
+// A half field (one parity) of nrhs right-hand sides in a given precision,
+// site-major: [rhs][h4][component block][Ns] (see the accessors).
 struct HalfField {
     int prec = DWF_PREC_FP64;
-    long stride = 0;   // elements per component block (>= V5h, padded)
-    long rstride = 0;  // elements between right-hand sides
+    long ns = 0;       // Ns
+    long rstride = 0;  // elements (16-byte vectors) between right-hand sides
+    long nstride = 0;  // FP16 norms between right-hand sides
     int nrhs = 0;
     DevBuf data, nrm;
-    int alloc(int prec, long V5h, int nrhs);
-    FD fd(int rhs0 = 0) const {
-        return FD{data.as<double2>() + rhs0 * rstride, stride, rstride};
-    }
-    FS fs(int rhs0 = 0) const {
-        return FS{data.as<float4>() + rhs0 * rstride, stride, rstride};
-    }
+    int alloc(int prec, long V5h, int Ns, int nrhs);
+    FD fd(int rhs0 = 0) const { return FD{data.as<double2>() + rhs0 * rstride, ns, rstride}; }
+    FS fs(int rhs0 = 0) const { return FS{data.as<float4>() + rhs0 * rstride, ns, rstride}; }
     FH fh(int rhs0 = 0) const {
-        return FH{data.as<uint4>() + rhs0 * rstride, nrm.as<float>() + rhs0 * stride, stride, rstride, stride};
+        return FH{data.as<uint4>() + rhs0 * rstride, nrm.as<float>() + rhs0 * nstride, ns, rstride, nstride};
     }
 };
 
@@ -98,7 +96,7 @@ struct Workspace {
     }
     HalfField& f(int i) { return *fields[i]; }
     // allocate n fields: precs[i] for field i
-    int alloc(const std::vector<int>& precs, long V5h, int nrhs_);
+    int alloc(const std::vector<int>& precs, long V5h, int Ns, int nrhs_);
     int alloc_state(int nrhs_);
 };
 

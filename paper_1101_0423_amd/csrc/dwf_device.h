@@ -8,9 +8,9 @@
 // Device layouts (one parity of the 4D checkerboard per "half field"):
 //   half 4D index  h4 = (x + Lx (y + Ly (z + Lz t))) / 2     (Lx even)
 //   half 5D index  i5 = s + Ns * h4                          (s fastest)
-//   FP64 spinor : double2 [12][stride]   block j = complex component j
-//   FP32 spinor : float4  [6][stride]    block j = complex components 2j, 2j+1
-//   FP16 spinor : 8 x binary16 [3][stride] + float norm[stride]
+//   FP64 spinor : double2 [h4][12][Ns]   block j = complex component j
+//   FP32 spinor : float4  [h4][6][Ns]    block j = complex components 2j, 2j+1
+//   FP16 spinor : 8 x binary16 [h4][3][Ns] + float norm[i5]
 //                 (value = half * norm, norm = max |component| of the site)
 //   complex component k = 3 * spin + colour; spins 0,1 are the + chirality
 //   (gamma_5 = diag(1,1,-1,-1) in the chiral basis).
@@ -28,71 +28,83 @@ namespace dwf {
 // spinor fields
 // ---------------------------------------------------------------------------
 
+// Every accessor addresses 5D half site i5 = s + Ns * h4 of right-hand side
+// rhs.  Layout per 4D site h4: [component block j][s][16 bytes], i.e. the
+// element of (i5, s, block j) is NB * i5 - (NB - 1) * s + j * Ns: the Ns
+// slices of one block are adjacent (one wave reads whole 256-byte runs) and
+// all of a 4D site's data is one contiguous chunk.
+
 struct FD {  // FP64 storage and arithmetic
     using real = double;
     double2* p;
-    long stride;   // elements per component block
+    long ns;       // Ns (elements between component blocks of a site)
     long rstride;  // elements between right-hand sides
-    __device__ __forceinline__ void load(int rhs, long i, double* v) const {
-        const double2* q = p + rhs * rstride + i;
+    __device__ __forceinline__ const double2* at(int rhs, long i, int s) const {
+        return p + rhs * rstride + 12 * i - 11 * (long)s;
+    }
+    __device__ __forceinline__ void load(int rhs, long i, int s, double* v) const {
+        const double2* q = at(rhs, i, s);
 #pragma unroll
         for (int j = 0; j < 12; ++j) {
-            double2 a = q[j * stride];
+            double2 a = q[j * ns];
             v[2 * j] = a.x;
             v[2 * j + 1] = a.y;
         }
     }
-    __device__ __forceinline__ void store(int rhs, long i, const double* v) const {
-        double2* q = p + rhs * rstride + i;
+    __device__ __forceinline__ void store(int rhs, long i, int s, const double* v) const {
+        double2* q = const_cast<double2*>(at(rhs, i, s));
 #pragma unroll
-        for (int j = 0; j < 12; ++j) q[j * stride] = make_double2(v[2 * j], v[2 * j + 1]);
+        for (int j = 0; j < 12; ++j) q[j * ns] = make_double2(v[2 * j], v[2 * j + 1]);
     }
-    __device__ __forceinline__ void load(int rhs, long i, float* v) const {
+    __device__ __forceinline__ void load(int rhs, long i, int s, float* v) const {
         double t[24];
-        load(rhs, i, t);
+        load(rhs, i, s, t);
 #pragma unroll
         for (int k = 0; k < 24; ++k) v[k] = (float)t[k];
     }
-    __device__ __forceinline__ void store(int rhs, long i, const float* v) const {
+    __device__ __forceinline__ void store(int rhs, long i, int s, const float* v) const {
         double t[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) t[k] = v[k];
-        store(rhs, i, t);
+        store(rhs, i, s, t);
     }
 };
 
 struct FS {  // FP32 storage
     using real = float;
     float4* p;
-    long stride;
+    long ns;
     long rstride;
-    __device__ __forceinline__ void load(int rhs, long i, float* v) const {
-        const float4* q = p + rhs * rstride + i;
+    __device__ __forceinline__ const float4* at(int rhs, long i, int s) const {
+        return p + rhs * rstride + 6 * i - 5 * (long)s;
+    }
+    __device__ __forceinline__ void load(int rhs, long i, int s, float* v) const {
+        const float4* q = at(rhs, i, s);
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            float4 a = q[j * stride];
+            float4 a = q[j * ns];
             v[4 * j] = a.x;
             v[4 * j + 1] = a.y;
             v[4 * j + 2] = a.z;
             v[4 * j + 3] = a.w;
         }
     }
-    __device__ __forceinline__ void store(int rhs, long i, const float* v) const {
-        float4* q = p + rhs * rstride + i;
+    __device__ __forceinline__ void store(int rhs, long i, int s, const float* v) const {
+        float4* q = const_cast<float4*>(at(rhs, i, s));
 #pragma unroll
-        for (int j = 0; j < 6; ++j) q[j * stride] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+        for (int j = 0; j < 6; ++j) q[j * ns] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
     }
-    __device__ __forceinline__ void load(int rhs, long i, double* v) const {
+    __device__ __forceinline__ void load(int rhs, long i, int s, double* v) const {
         float t[24];
-        load(rhs, i, t);
+        load(rhs, i, s, t);
 #pragma unroll
         for (int k = 0; k < 24; ++k) v[k] = t[k];
     }
-    __device__ __forceinline__ void store(int rhs, long i, const double* v) const {
+    __device__ __forceinline__ void store(int rhs, long i, int s, const double* v) const {
         float t[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) t[k] = (float)v[k];
-        store(rhs, i, t);
+        store(rhs, i, s, t);
     }
 };
 
@@ -101,47 +113,50 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 struct FH {  // binary16 storage with one FP32 scale per 5D site; FP32 arithmetic
     using real = float;
     uint4* p;
-    float* nrm;
-    long stride;
+    float* nrm;     // [i5]
+    long ns;
     long rstride;   // data elements between right-hand sides
     long nrstride;  // norm elements between right-hand sides
-    __device__ __forceinline__ void load(int rhs, long i, float* v) const {
-        const uint4* q = p + rhs * rstride + i;
+    __device__ __forceinline__ const uint4* at(int rhs, long i, int s) const {
+        return p + rhs * rstride + 3 * i - 2 * (long)s;
+    }
+    __device__ __forceinline__ void load(int rhs, long i, int s, float* v) const {
+        const uint4* q = at(rhs, i, s);
         float n = nrm[rhs * nrstride + i];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            uint4 a = q[j * stride];
+            uint4 a = q[j * ns];
             half8_t h = __builtin_bit_cast(half8_t, a);
 #pragma unroll
             for (int k = 0; k < 8; ++k) v[8 * j + k] = (float)h[k] * n;
         }
     }
-    __device__ __forceinline__ void store(int rhs, long i, const float* v) const {
+    __device__ __forceinline__ void store(int rhs, long i, int s, const float* v) const {
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
         float inv = m > 0.f ? 1.f / m : 0.f;
-        uint4* q = p + rhs * rstride + i;
+        uint4* q = const_cast<uint4*>(at(rhs, i, s));
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             half8_t h;
 #pragma unroll
             for (int k = 0; k < 8; ++k) h[k] = (_Float16)(v[8 * j + k] * inv);
-            q[j * stride] = __builtin_bit_cast(uint4, h);
+            q[j * ns] = __builtin_bit_cast(uint4, h);
         }
         nrm[rhs * nrstride + i] = m;
     }
-    __device__ __forceinline__ void load(int rhs, long i, double* v) const {
+    __device__ __forceinline__ void load(int rhs, long i, int s, double* v) const {
         float t[24];
-        load(rhs, i, t);
+        load(rhs, i, s, t);
 #pragma unroll
         for (int k = 0; k < 24; ++k) v[k] = t[k];
     }
-    __device__ __forceinline__ void store(int rhs, long i, const double* v) const {
+    __device__ __forceinline__ void store(int rhs, long i, int s, const double* v) const {
         float t[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) t[k] = (float)v[k];
-        store(rhs, i, t);
+        store(rhs, i, s, t);
     }
 };
 
@@ -152,6 +167,10 @@ struct FH {  // binary16 storage with one FP32 scale per 5D site; FP32 arithmeti
 template <class Real>
 struct LdsLink {
     static constexpr int STR = sizeof(Real) == 4 ? 20 : 18;  // 16-byte aligned rows
+    // per-site stride: 8 links plus 16 bytes, so that the sites read together
+    // by one wave start on different LDS banks
+    static constexpr int SITE = 8 * STR + (sizeof(Real) == 4 ? 4 : 2);
+    static __device__ __forceinline__ int at(int l) { return (l >> 3) * SITE + (l & 7) * STR; }
 };
 
 template <class Real>
@@ -171,16 +190,21 @@ __device__ __forceinline__ void su3_third_row(Real* u) {
 #undef IM
 }
 
+// stage(lds, site0, nsites, tid, T, sc): the 8 links of nsites sites, link l
+// (= 8 * site + entry) multiplied by sc(l), as row-major 3x3 in LDS.
 struct LinkD18 {
     using real = double;
     const double* p;  // [h4][8][18]
-    __device__ __forceinline__ void stage(double* lds, long site0, int nsites, int tid, int T) const {
+    template <class Sc>
+    __device__ __forceinline__ void stage(double* lds, long site0, int nsites, int tid, int T, const Sc& sc) const {
         const double2* src = (const double2*)(p + site0 * 8 * 18);
         int n2 = nsites * 8 * 9;
         for (int i = tid; i < n2; i += T) {
             double2 q = src[i];
-            lds[2 * i] = q.x;
-            lds[2 * i + 1] = q.y;
+            int l = i / 9, c = i - 9 * l;
+            double f = sc(l);
+            lds[LdsLink<double>::at(l) + 2 * c] = f * q.x;
+            lds[LdsLink<double>::at(l) + 2 * c + 1] = f * q.y;
         }
     }
 };
@@ -188,14 +212,16 @@ struct LinkD18 {
 struct LinkS18 {
     using real = float;
     const float* p;  // [h4][8][18]
-    __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T) const {
+    template <class Sc>
+    __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T, const Sc& sc) const {
         const float2* src = (const float2*)(p + site0 * 8 * 18);
         int n2 = nsites * 8 * 9;
         for (int i = tid; i < n2; i += T) {
             int l = i / 9, c = i - 9 * l;
             float2 q = src[i];
-            lds[l * 20 + 2 * c] = q.x;
-            lds[l * 20 + 2 * c + 1] = q.y;
+            float f = sc(l);
+            lds[LdsLink<float>::at(l) + 2 * c] = f * q.x;
+            lds[LdsLink<float>::at(l) + 2 * c + 1] = f * q.y;
         }
     }
 };
@@ -203,7 +229,8 @@ struct LinkS18 {
 struct LinkS12 {
     using real = float;
     const float* p;  // [h4][8][12]
-    __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T) const {
+    template <class Sc>
+    __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T, const Sc& sc) const {
         const float4* src = (const float4*)(p + site0 * 8 * 12);
         int nl = nsites * 8;
         for (int l = tid; l < nl; l += T) {
@@ -214,8 +241,9 @@ struct LinkS12 {
                 u[4 * j] = q.x; u[4 * j + 1] = q.y; u[4 * j + 2] = q.z; u[4 * j + 3] = q.w;
             }
             su3_third_row(u);
+            const float f = sc(l);
 #pragma unroll
-            for (int k = 0; k < 18; ++k) lds[l * 20 + k] = u[k];
+            for (int k = 0; k < 18; ++k) lds[LdsLink<float>::at(l) + k] = f * u[k];
         }
     }
 };
@@ -223,7 +251,8 @@ struct LinkS12 {
 struct LinkH12 {
     using real = float;
     const _Float16* p;  // [h4][8][12]
-    __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T) const {
+    template <class Sc>
+    __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T, const Sc& sc) const {
         const uint2* src = (const uint2*)(p + site0 * 8 * 12);
         int nl = nsites * 8;
         typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
@@ -236,8 +265,9 @@ struct LinkH12 {
                 for (int k = 0; k < 4; ++k) u[4 * j + k] = (float)h[k];
             }
             su3_third_row(u);
+            const float f = sc(l);
 #pragma unroll
-            for (int k = 0; k < 18; ++k) lds[l * 20 + k] = u[k];
+            for (int k = 0; k < 18; ++k) lds[LdsLink<float>::at(l) + k] = f * u[k];
         }
     }
 };
@@ -283,7 +313,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb, int on) {
 
 template <int MU, int SIG, class Real>
 __device__ __forceinline__ void hop_dir(const Real* __restrict__ psi, const Real* __restrict__ U,
-                                        Real sc, Real* __restrict__ acc) {
+                                        Real* __restrict__ acc) {
     Real h0[6], h1[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -317,7 +347,6 @@ __device__ __forceinline__ void hop_dir(const Real* __restrict__ psi, const Real
             r1 += ur * h1[2 * b] - ui * h1[2 * b + 1];
             i1 += ur * h1[2 * b + 1] + ui * h1[2 * b];
         }
-        if (MU == 3) { r0 *= sc; i0 *= sc; r1 *= sc; i1 *= sc; }
         u0[2 * a] = r0; u0[2 * a + 1] = i0;
         u1[2 * a] = r1; u1[2 * a + 1] = i1;
     }
@@ -368,30 +397,33 @@ __device__ __forceinline__ void neighbours(const Geom& g, int h4, int par, int* 
     tbw = (t == 0);
 }
 
+// The 8 directions of Eq. (14) for one (site, s) lane.  The staged links
+// already carry the factor -1/2 (and the sign of links that cross an
+// antiperiodic time boundary).  (Keeping two directions' loads in flight per
+// wave costs a wave of occupancy and measured slower on gfx950.)
 template <class Real, class F>
 __device__ __forceinline__ void hop_site(const F& in, int rhs, int s, int Ns, const int* nb,
-                                         const Real* __restrict__ lk, Real sf, Real sb, Real* acc) {
+                                         const Real* __restrict__ lk, Real* acc) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) acc[k] = 0;
     constexpr int LS = LdsLink<Real>::STR;
-    Real psi[24];
     Real U[18];
-#define DWF_HOP(MU)                                                        \
-    {                                                                      \
-        in.load(rhs, (long)nb[MU] * Ns + s, psi);                          \
-        _Pragma("unroll") for (int k = 0; k < 18; ++k) U[k] = lk[(MU) * LS + k]; \
-        hop_dir<MU, -1>(psi, U, sf, acc);                                  \
-        in.load(rhs, (long)nb[4 + (MU)] * Ns + s, psi);                    \
-        _Pragma("unroll") for (int k = 0; k < 18; ++k) U[k] = lk[(4 + (MU)) * LS + k]; \
-        hop_dir<MU, +1>(psi, U, sb, acc);                                  \
+    Real pa[24];
+#define DWF_STEP(MU, SIG, L)                                                   \
+    {                                                                          \
+        in.load(rhs, (long)nb[L] * Ns + s, s, pa);                             \
+        _Pragma("unroll") for (int k = 0; k < 18; ++k) U[k] = lk[(L) * LS + k]; \
+        hop_dir<MU, SIG>(pa, U, acc);                                          \
     }
-    DWF_HOP(0)
-    DWF_HOP(1)
-    DWF_HOP(2)
-    DWF_HOP(3)
-#undef DWF_HOP
-#pragma unroll
-    for (int k = 0; k < 24; ++k) acc[k] *= (Real)-0.5;
+    DWF_STEP(0, -1, 0)
+    DWF_STEP(0, +1, 4)
+    DWF_STEP(1, -1, 1)
+    DWF_STEP(1, +1, 5)
+    DWF_STEP(2, -1, 2)
+    DWF_STEP(2, +1, 6)
+    DWF_STEP(3, -1, 3)
+    DWF_STEP(3, +1, 7)
+#undef DWF_STEP
 }
 
 // ---------------------------------------------------------------------------
@@ -542,10 +574,15 @@ __host__ __device__ inline int hbuf_site_stride(int Ns) {
     return Ns * 24 + (sizeof(Real) == 4 ? 12 : 6);
 }
 
+// LDS: [links G x 8 x LS reals][neighbours G x 8 ints][column buffer][reduction]
+template <class Real>
+__host__ __device__ inline size_t smem_links(int G, bool hop) {
+    return hop ? (size_t)G * LdsLink<Real>::SITE * sizeof(Real) + (size_t)G * 8 * sizeof(int) : 0;
+}
+
 template <class Real>
 __host__ __device__ inline size_t kernel_smem(int G, int Ns, bool hop, bool mix) {
-    size_t b = 0;
-    if (hop) b += (size_t)G * 8 * LdsLink<Real>::STR * sizeof(Real);
+    size_t b = smem_links<Real>(G, hop);
     if (mix) b += (size_t)G * hbuf_site_stride<Real>(Ns) * sizeof(Real);
     b = (b + 15) & ~(size_t)15;
     b += 16 * sizeof(double);
@@ -568,9 +605,9 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
     }
 
     Real* lk = (Real*)smem;
-    Real* hb = lk + (HOP ? g.G * 8 * LS : 0);
-    size_t off = (HOP ? (size_t)g.G * 8 * LS * sizeof(Real) : 0) +
-                 (MIX ? (size_t)g.G * hbuf_site_stride<Real>(Ns) * sizeof(Real) : 0);
+    int* nbl = (int*)(lk + g.G * LdsLink<Real>::SITE);
+    Real* hb = (Real*)(smem + smem_links<Real>(g.G, HOP));
+    size_t off = smem_links<Real>(g.G, HOP) + (MIX ? (size_t)g.G * hbuf_site_stride<Real>(Ns) * sizeof(Real) : 0);
     off = (off + 15) & ~(size_t)15;
     double* red = (double*)(smem + off);
 
@@ -584,18 +621,31 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
     const int hs = hbuf_site_stride<Real>(Ns);
 
     int nb[8];
-    Real sf = 1, sb = 1;
     if constexpr (HOP) {
-        links.stage(lk, site0, nsites, tid, T);
-        if (act) {
-            int tf, tb;
-            neighbours(g, (int)h4, g.out_parity, nb, tf, tb);
-            if (g.antiper) {
-                sf = tf ? (Real)-1 : (Real)1;
-                sb = tb ? (Real)-1 : (Real)1;
+        // links scaled by -1/2 (Eq. (14)); links crossing the t boundary also
+        // carry the antiperiodic sign
+        const int vol3h = g.Lxh * g.Ly * g.Lz;
+        auto sc = [&](int l) -> Real {
+            const int k = l & 7;
+            if (g.antiper && (k & 3) == 3) {
+                const int t = (int)((site0 + (l >> 3)) / vol3h);
+                if ((k == 3 && t == g.Lt - 1) || (k == 7 && t == 0)) return (Real)0.5;
             }
+            return (Real)-0.5;
+        };
+        links.stage(lk, site0, nsites, tid, T, sc);
+        // neighbour indices, once per site
+        if (tid < nsites) {
+            int q[8], tf, tb;
+            neighbours(g, (int)(site0 + tid), g.out_parity, q, tf, tb);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) nbl[tid * 8 + k] = q[k];
         }
         __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) nb[k] = nbl[sl * 8 + k];
+        }
     }
 
     for (int rhs = 0; rhs < o.nrhs; ++rhs) {
@@ -603,9 +653,9 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
         Real v[24];
         if (act) {
             if constexpr (HOP)
-                hop_site<Real>(in, rhs, s, Ns, nb, lk + sl * 8 * LS, sf, sb, v);
+                hop_site<Real>(in, rhs, s, Ns, nb, lk + sl * LdsLink<Real>::SITE, v);
             else
-                pro(rhs, i5, v);
+                pro(rhs, i5, s, v);
         }
         if constexpr (MIX) {
             if (act) {
@@ -644,7 +694,7 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
             }
         }
         double part = 0;
-        if (act) part = epi(rhs, i5, v);
+        if (act) part = epi(rhs, i5, s, v);
         if constexpr (Epi::kReduce) {
             double tot = block_sum(part, red);
             if (tid == 0) o.partials[(long)rhs * gridDim.x + blockIdx.x] = tot;
@@ -678,7 +728,7 @@ template <class F>
 struct ProLoad {
     F f;
     template <class Real>
-    __device__ __forceinline__ void operator()(int rhs, long i, Real* v) const { f.load(rhs, i, v); }
+    __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const { f.load(rhs, i, s, v); }
 };
 
 // CG direction update, Algorithm 1: p = r + beta p (or p = r when reset[rhs]).
@@ -689,16 +739,16 @@ struct ProCgE {
     const double* beta;
     const int* reset;  // per right-hand side; NULL = never reset
     template <class Real>
-    __device__ __forceinline__ void operator()(int rhs, long i, Real* v) const {
-        r.load(rhs, i, v);
+    __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const {
+        r.load(rhs, i, s, v);
         if (!(reset && reset[rhs])) {
             Real b = (Real)beta[rhs];
             Real q[24];
-            p.load(rhs, i, q);
+            p.load(rhs, i, s, q);
 #pragma unroll
             for (int k = 0; k < 24; ++k) v[k] += b * q[k];
         }
-        p.store(rhs, i, v);
+        p.store(rhs, i, s, v);
     }
 };
 
@@ -719,8 +769,8 @@ struct EpiStore {
     static constexpr bool kReduce = RED;
     F out;
     template <class Real>
-    __device__ __forceinline__ double operator()(int rhs, long i, Real* v) const {
-        out.store(rhs, i, v);
+    __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
+        out.store(rhs, i, s, v);
         return RED ? norm2_24(v) : 0.0;
     }
 };
@@ -729,7 +779,7 @@ struct EpiStore {
 struct EpiNorm {
     static constexpr bool kReduce = true;
     template <class Real>
-    __device__ __forceinline__ double operator()(int, long, Real* v) const { return norm2_24(v); }
+    __device__ __forceinline__ double operator()(int, long, int, Real* v) const { return norm2_24(v); }
 };
 
 // out = ca * a + cv * (g5 ? gamma_5 v : v)
@@ -740,16 +790,16 @@ struct EpiLin {
     FO out;
     double ca, cv;
     template <class Real>
-    __device__ __forceinline__ double operator()(int rhs, long i, Real* v) const {
+    __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         Real w[24];
-        a.load(rhs, i, w);
+        a.load(rhs, i, s, w);
         const Real A = (Real)ca, B = (Real)cv;
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
             Real vk = (G5 && k >= 12) ? -v[k] : v[k];
             w[k] = A * w[k] + B * vk;
         }
-        out.store(rhs, i, w);
+        out.store(rhs, i, s, w);
         return RED ? norm2_24(w) : 0.0;
     }
 };
@@ -761,12 +811,12 @@ struct EpiCgB {
     FP p;
     FU u;
     template <class Real>
-    __device__ __forceinline__ double operator()(int rhs, long i, Real* v) const {
+    __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         Real w[24];
-        p.load(rhs, i, w);
+        p.load(rhs, i, s, w);
 #pragma unroll
         for (int k = 0; k < 24; ++k) w[k] = k < 12 ? w[k] - v[k] : w[k] + v[k];
-        u.store(rhs, i, w);
+        u.store(rhs, i, s, w);
         return norm2_24(w);
     }
 };
@@ -780,19 +830,19 @@ struct EpiCgD {
     FY y;
     const double* alpha;
     template <class Real>
-    __device__ __forceinline__ double operator()(int rhs, long i, Real* v) const {
+    __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         const Real a = (Real)alpha[rhs];
         Real uu[24], w[24];
-        u.load(rhs, i, uu);
-        r.load(rhs, i, w);
+        u.load(rhs, i, s, uu);
+        r.load(rhs, i, s, w);
 #pragma unroll
         for (int k = 0; k < 24; ++k) w[k] -= a * (uu[k] - v[k]);
-        r.store(rhs, i, w);
+        r.store(rhs, i, s, w);
         Real yy[24];
-        y.load(rhs, i, yy);
+        y.load(rhs, i, s, yy);
 #pragma unroll
         for (int k = 0; k < 24; ++k) yy[k] += a * uu[k];
-        y.store(rhs, i, yy);
+        y.store(rhs, i, s, yy);
         return norm2_24(w);
     }
 };
@@ -807,22 +857,22 @@ struct EpiOuter {
     FYH yh;
     FR r;
     FY y;
-    __device__ __forceinline__ double operator()(int rhs, long i, double* v) const {
+    __device__ __forceinline__ double operator()(int rhs, long i, int s, double* v) const {
         double bb[24], yy[24];
-        b2.load(rhs, i, bb);
-        yh.load(rhs, i, yy);
-        double s = 0;
+        b2.load(rhs, i, s, bb);
+        yh.load(rhs, i, s, yy);
+        double nrm = 0;
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
             bb[k] = bb[k] - yy[k] + v[k];
-            s += bb[k] * bb[k];
+            nrm += bb[k] * bb[k];
         }
-        r.store(rhs, i, bb);
+        r.store(rhs, i, s, bb);
         double z[24];
 #pragma unroll
         for (int k = 0; k < 24; ++k) z[k] = 0;
-        y.store(rhs, i, z);
-        return s;
+        y.store(rhs, i, s, z);
+        return nrm;
     }
 };
 
@@ -833,17 +883,17 @@ struct EpiTrueRes {
     static constexpr bool kReduce = true;
     FB b;
     FX xx;
-    __device__ __forceinline__ double operator()(int rhs, long i, double* v) const {
+    __device__ __forceinline__ double operator()(int rhs, long i, int s, double* v) const {
         double bb[24], w[24];
-        b.load(rhs, i, bb);
-        xx.load(rhs, i, w);
-        double s = 0;
+        b.load(rhs, i, s, bb);
+        xx.load(rhs, i, s, w);
+        double nrm = 0;
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
             double d = bb[k] - w[k] - v[k];
-            s += d * d;
+            nrm += d * d;
         }
-        return s;
+        return nrm;
     }
 };
 

@@ -49,9 +49,9 @@ __global__ void k_host_to_half(const double* __restrict__ host, Dims d, F ev, F 
     }
     long i5 = s + (long)d.Ns * (n4 >> 1);
     if (parity_of(n4, d))
-        od.store(rhs, i5, v);
+        od.store(rhs, i5, s, v);
     else
-        ev.store(rhs, i5, v);
+        ev.store(rhs, i5, s, v);
 }
 
 template <class F>
@@ -64,9 +64,9 @@ __global__ void k_half_to_host(double* __restrict__ host, Dims d, F ev, F od) {
     long i5 = s + (long)d.Ns * (n4 >> 1);
     double v[24];
     if (parity_of(n4, d))
-        od.load(rhs, i5, v);
+        od.load(rhs, i5, s, v);
     else
-        ev.load(rhs, i5, v);
+        ev.load(rhs, i5, s, v);
     double2* dst = (double2*)(host + ((long)rhs * d.V5 + n5) * 24);
 #pragma unroll
     for (int j = 0; j < 12; ++j) dst[j] = make_double2(v[2 * j], v[2 * j + 1]);
@@ -78,8 +78,9 @@ __global__ void k_convert(FA a, FB b, long n) {
     int rhs = blockIdx.y;
     if (i >= n) return;
     double v[24];
-    a.load(rhs, i, v);
-    b.store(rhs, i, v);
+    const int s = (int)(i % a.ns);
+    a.load(rhs, i, s, v);
+    b.store(rhs, i, s, v);
 }
 
 template <class F>
@@ -90,7 +91,7 @@ __global__ void k_zero(F f, long n) {
     double v[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = 0;
-    f.store(rhs, i, v);
+    f.store(rhs, i, (int)(i % f.ns), v);
 }
 
 template <class F>
@@ -100,8 +101,9 @@ __global__ void k_copy(F dst, F src, long n, const int* mask) {
     if (i >= n) return;
     if (mask && !mask[rhs]) return;
     double v[24];
-    src.load(rhs, i, v);
-    dst.store(rhs, i, v);
+    const int s = (int)(i % src.ns);
+    src.load(rhs, i, s, v);
+    dst.store(rhs, i, s, v);
 }
 
 // yhat += y (FP64 accumulation of the low-precision correction), Alg. 2
@@ -112,11 +114,12 @@ __global__ void k_acc(FD yh, F y, long n, const int* mask) {
     if (i >= n) return;
     if (mask && !mask[rhs]) return;
     double a[24], b[24];
-    yh.load(rhs, i, a);
-    y.load(rhs, i, b);
+    const int s = (int)(i % yh.ns);
+    yh.load(rhs, i, s, a);
+    y.load(rhs, i, s, b);
 #pragma unroll
     for (int k = 0; k < 24; ++k) a[k] += b[k];
-    yh.store(rhs, i, a);
+    yh.store(rhs, i, s, a);
 }
 
 // Gauge links of output parity par, one thread per (site, entry):

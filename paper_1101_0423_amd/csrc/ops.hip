@@ -162,7 +162,7 @@ int apply_impl(dwf_ctx* c, int op, int prec, LF e, LF o_, const double* in_dev, 
     auto& slot = c->ws[key];
     if (!slot) {
         slot.reset(new Workspace);
-        if ((rc = slot->alloc(std::vector<int>(NAPPLY, prec), c->V5h, nrhs))) {
+        if ((rc = slot->alloc(std::vector<int>(NAPPLY, prec), c->V5h, c->Ns, nrhs))) {
             slot.reset();
             return rc;
         }

@@ -193,7 +193,7 @@ int run_solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dw
         std::vector<int> precs(NF64, DWF_PREC_FP64);
         for (int i = 0; i < 5; ++i) precs.push_back(prec);
         precs.push_back(prec == DWF_PREC_FP64 ? DWF_PREC_FP64 : DWF_PREC_FP32);  // y
-        if ((rc = slot->alloc(precs, c->V5h, nrhs)) || (rc = slot->alloc_state(nrhs))) {
+        if ((rc = slot->alloc(precs, c->V5h, c->Ns, nrhs)) || (rc = slot->alloc_state(nrhs))) {
             slot.reset();
             return rc;
         }
