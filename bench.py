@@ -76,6 +76,40 @@ def cpu_baseline(w, U, b, n1=1, n2=5):
                 seconds_per_iteration=per_it)
 
 
+KERNEL_KEYS = [("ProCgE", "cg_dir_m5t"), ("EpiCgD", "hop_oe_m5_cgupd"), ("EpiCgB", "hop_oe_g5_sub"),
+               ("k_finish", "finish_reduction"), ("EpiOuter", "outer_residual_fp64")]
+
+
+def kernel_label(name):
+    for key, label in KERNEL_KEYS:
+        if key in name:
+            return label
+    if "k_dwf" in name and "true, 3, dwf::ProLoad<dwf::FS>, dwf::EpiStore<dwf::FS" in name:
+        return "hop_eo_m5t"
+    if "k_dwf" in name and "true, 2, dwf::ProLoad<dwf::FS>, dwf::EpiStore<dwf::FS" in name:
+        return "hop_eo_m5"
+    return name[:90]
+
+
+def summarize_rocpd(path):
+    import sqlite3
+    db = sqlite3.connect(path)
+    tabs = {r[0] for r in db.execute("select name from sqlite_master")}
+    if "pmc_events" in tabs and db.execute("select count(*) from pmc_events").fetchone()[0] > 0:
+        rows = db.execute("select name, counter_name, count(*), avg(counter_value), avg(duration) "
+                          "from pmc_events group by name, counter_name order by avg(duration) desc").fetchall()
+        print(f"{'kernel':40s} {'counter':12s} {'dispatches':>10s} {'avg value':>14s} {'avg us':>9s}")
+        for name, ctr, n, val, dur in rows:
+            print(f"{kernel_label(name):40s} {ctr:12s} {n:10d} {val:14.1f} {dur / 1e3:9.1f}")
+        return
+    rows = db.execute("select name, count(*), sum(duration), avg(duration) from kernels "
+                      "group by name order by sum(duration) desc").fetchall()
+    tot = sum(r[2] for r in rows)
+    print(f"{'kernel':40s} {'calls':>8s} {'total ms':>10s} {'avg us':>9s} {'share':>6s}")
+    for name, n, s, a in rows[:20]:
+        print(f"{kernel_label(name):40s} {n:8d} {s / 1e6:10.2f} {a / 1e3:9.2f} {100 * s / tot:5.1f}%")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,7 +118,15 @@ def main():
     ap.add_argument("--prec", choices=sorted(WORKLOADS), default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=20)
+    ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
+                    help="kernels: one short solve without graphs, then each inner kernel timed "
+                         "(the driver for counter runs)")
+    ap.add_argument("--summarize-rocpd", metavar="DB", help="print per-kernel statistics of a rocprofv3 "
+                    "results database (kernel trace or --pmc) and exit")
     args = ap.parse_args()
+    if args.summarize_rocpd:
+        summarize_rocpd(args.summarize_rocpd)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; there is no multi-GPU path "
               "(a single solve would shard by 4D domain decomposition, see DESIGN.md)", file=sys.stderr)
@@ -107,6 +149,14 @@ def main():
     bd = torch.from_numpy(b).cuda()
     xd = torch.zeros_like(bd)
     params = dwf.default_params(inner_prec=prec, link_compress=lc, tol=1e-10)
+    if args.mode == "kernels":
+        kp = dwf.default_params(inner_prec=prec, link_compress=lc, use_graph=0, maxiter=40)
+        st, rc = ctx.solve_dev(bd, xd, params=kp)
+        ms, by = ctx.time_kernels(params=kp, launches=5)
+        print(json.dumps(dict(mode="kernels", workload=wname, ms={k: ms[k] for k in ms},
+                              bytes={k: by[k] for k in by})), flush=True)
+        ctx.close()
+        return
     for i in range(args.warmup):
         st, rc = ctx.solve_dev(bd, xd, params=params)
         print(f"[bench] warmup {i}: rc={rc} {st[0]}", file=sys.stderr, flush=True)
