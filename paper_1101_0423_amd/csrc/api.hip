@@ -69,8 +69,8 @@ int Workspace::alloc(const std::vector<int>& precs, long V5h, int Ns, int nrhs_)
 }
 
 int Workspace::alloc_state(int n) {
-    // 6 double arrays + 4 int arrays of length n
-    size_t nd = 6 * (size_t)n, ni = 4 * (size_t)n;
+    // 6 double arrays + 5 int arrays of length n
+    size_t nd = 6 * (size_t)n, ni = 5 * (size_t)n;
     int rc = state.alloc(nd * sizeof(double) + ni * sizeof(int));
     if (rc) return rc;
     double* d = state.as<double>();
@@ -85,6 +85,7 @@ int Workspace::alloc_state(int n) {
     st.iters = i + n;
     st.status = i + 2 * n;
     st.maxiter = i + 3 * n;
+    st.emode = i + 4 * n;
     hipError_t e = hipMemset(state.p, 0, state.bytes);
     if (e != hipSuccess) return fail(DWF_EDEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
     return DWF_OK;
@@ -112,6 +113,7 @@ dwf::Geom dwf_ctx::geom(int out_parity, bool fp64) const {
 }
 
 const TableSet* dwf_ctx::table_set(double mq_val, int* rc) {
+    std::lock_guard<std::mutex> lk(tables_mtx);
     auto it = tables.find(mq_val);
     if (it != tables.end()) {
         *rc = DWF_OK;
@@ -244,6 +246,7 @@ int dwf_create(dwf_ctx** out, const double* gauge, const int dims[4], int Ns, do
 
 void dwf_destroy(dwf_ctx* c) {
     if (!c) return;
+    server_detach(c);
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     hipStream_t s = c->stream;
@@ -298,7 +301,8 @@ int dwf_solve_dev(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, cons
     std::lock_guard<std::mutex> lk(c->mtx);
     DWF_HIP(hipSetDevice(c->device));
     hipStream_t s = stream ? (hipStream_t)stream : c->stream;
-    return solve(c, b_dev, x_dev, nrhs, p, stats, s, nullptr);
+    if (p.link_compress < -1 || p.link_compress > 1) return fail(DWF_EINVAL, "link_compress must be -1, 0 or 1");
+    return solve(c, b_dev, x_dev, nrhs, p, stats, s);
 }
 
 int dwf_time_kernels(dwf_ctx* c, const dwf_solve_params* params, int nrhs, int launches, double ms[5],

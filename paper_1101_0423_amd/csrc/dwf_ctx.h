@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <condition_variable>
 #include <string>
 #include <vector>
 
@@ -100,6 +101,51 @@ struct Workspace {
     int alloc_state(int nrhs_);
 };
 
+// Phases of one right-hand side ("slot") of a solve engine.
+enum SlotPhase { PH_FREE = 0, PH_SETUP, PH_OUTER, PH_INNER, PH_FINAL, PH_DONE };
+
+// Outcome of one slot, read when it is retired.
+struct SlotResult {
+    int status = DWF_OK;
+    int iters = 0, restarts = 0, reliable_updates = 0, fallback = 0;
+    double true_residual = 0, schur_residual = 0;
+    double seconds = 0;  // host wall time from admission to the final check
+    double flops = 0;    // paper-convention flops of this right-hand side
+    double bytes = 0;    // algorithmic HBM bytes of this right-hand side
+};
+
+// A solve engine: K slots that share the multi-right-hand-side kernels of one
+// operator, inner precision and link format.  Each slot carries its own
+// quark mass, tolerances and outer-loop state, and can be admitted or retired
+// while the others iterate.  All work goes to one HIP stream.
+class EngineBase {
+  public:
+    virtual ~EngineBase() {}
+    virtual int capacity() const = 0;
+    virtual int phase(int slot) const = 0;
+    virtual int busy() const = 0;  // slots not free
+    virtual int pending() const = 0;  // slots neither free nor done
+    virtual void set_stream(hipStream_t s) = 0;
+    virtual void set_use_graph(bool on) = 0;
+    virtual void set_replay_cap(int n) = 0;  // graph replays per round (default 64)
+    // Convert one right-hand side (device, host layout) into the slot; x0 is
+    // an initial guess (device, host layout) or NULL.
+    virtual int admit(int slot, const double* b_dev, const double* x0_dev, double mq,
+                      const dwf_solve_params& p) = 0;
+    // One scheduling round: setup, outer steps, reconstructions, and a run of
+    // inner iterations for every live slot.  Ends with the stream idle.
+    virtual int tick() = 0;
+    // Write the solution of a PH_DONE slot (device, host layout) and free it.
+    virtual int retire(int slot, double* x_dev, SlotResult* res) = 0;
+    virtual int time_kernels(int launches, double* ms, double* bytes) = 0;
+    virtual size_t device_bytes() const = 0;
+};
+
+int make_engine(dwf_ctx* c, const dwf_solve_params& p, int K, hipStream_t s, std::unique_ptr<EngineBase>* out);
+int link_format(const dwf_solve_params& p);
+// device bytes of an engine with K slots (fields, tables, state, reductions)
+size_t engine_bytes(const dwf_ctx* c, int inner_prec, int K);
+
 }  // namespace dwf
 
 struct dwf_ctx {
@@ -114,8 +160,10 @@ struct dwf_ctx {
     int G64, G32;  // 4D sites per workgroup for FP64 and FP32/FP16 kernels
     dwf::DevBuf links[2][dwf::LINK_NFMT];  // [output parity][format]
     std::map<double, std::unique_ptr<dwf::TableSet>> tables;
+    std::mutex tables_mtx;  // the table map is shared with the server's threads
     std::mutex mtx;  // one call at a time per context
     std::map<std::string, std::unique_ptr<dwf::Workspace>> ws;
+    std::map<std::string, std::unique_ptr<dwf::EngineBase>> engines;  // dwf_solve engines by kind
     dwf::DevBuf partials;  // block sums
     size_t partials_bytes = 0;
     std::string gauge_key;
@@ -153,15 +201,18 @@ hipError_t launch_dwf(const Geom& g, const F& in, const LF& links, const Real* t
 // finish kernel modes
 enum FinMode { FIN_AUX = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_OUTER = 3 };
 
-hipError_t launch_finish(const double* partials, int nblocks, int nrhs, CgState st, int mode, hipStream_t s);
+// mask (per right-hand side, NULL = all) restricts FIN_AUX and FIN_OUTER
+hipError_t launch_finish(const double* partials, int nblocks, int nrhs, CgState st, int mode, hipStream_t s,
+                         const int* mask = nullptr);
 
 // elementwise / layout kernels (layout.hip)
+// rhs0: first right-hand side of the half fields that the conversion covers
 hipError_t host_to_half(const dwf_ctx* c, const double* host, int nrhs, HalfField& even, HalfField& odd,
-                        hipStream_t s);
+                        hipStream_t s, int rhs0 = 0);
 hipError_t half_to_host(const dwf_ctx* c, const HalfField& even, const HalfField& odd, int nrhs, double* host,
-                        hipStream_t s);
+                        hipStream_t s, int rhs0 = 0);
 hipError_t half_convert(const dwf_ctx* c, const HalfField& src, HalfField& dst, int nrhs, hipStream_t s);
-hipError_t half_zero(const dwf_ctx* c, HalfField& f, int nrhs, hipStream_t s);
+hipError_t half_zero(const dwf_ctx* c, HalfField& f, int nrhs, hipStream_t s, const int* mask = nullptr);
 hipError_t half_copy(const dwf_ctx* c, HalfField& dst, const HalfField& src, int nrhs, const int* mask,
                      hipStream_t s);
 hipError_t half_acc(const dwf_ctx* c, HalfField& yhat, const HalfField& y, int nrhs, const int* mask,
@@ -171,9 +222,12 @@ hipError_t pack_links(const dwf_ctx* c, const double* gauge_dev, hipStream_t s);
 // operator application on half fields (ops.hip)
 int apply_op(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs, hipStream_t s);
 
-// the solver (solver.hip)
+// the solver (solver.hip): nrhs right-hand sides, all with the context's mq
 int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params& p,
-          dwf_solve_stats* stats, hipStream_t s, const double* mq_per_rhs);
+          dwf_solve_stats* stats, hipStream_t s);
+
+// the request server (server.hip): stop and forget the context's engines
+void server_detach(dwf_ctx* c);
 
 int time_inner_kernels(dwf_ctx* c, const dwf_solve_params& p, int nrhs, int launches, double* ms, double* bytes);
 

@@ -718,6 +718,8 @@ struct CgState {
     int* iters;         // inner iterations done (all cycles)
     int* status;        // 0 running, 1 converged, 2 breakdown, 3 iteration cap, 4 diverged
     int* maxiter;
+    int* emode;         // direction update of the next kernel E: 0 p = r + beta p, 1 p = r
+                        // (fresh Krylov space), 2 p kept; cleared once E has run
 };
 
 // ---------------------------------------------------------------------------
@@ -731,17 +733,24 @@ struct ProLoad {
     __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const { f.load(rhs, i, s, v); }
 };
 
-// CG direction update, Algorithm 1: p = r + beta p (or p = r when reset[rhs]).
+// CG direction update, Algorithm 1: p = r + beta p.  With a per-right-hand-
+// side mode (emode, NULL = 0): 1 restarts from p = r, 2 keeps p as it is (the
+// reliable-update restart), so the kernel only forms M5^T gamma_5 p.
 template <class FR, class FP>
 struct ProCgE {
     FR r;
     FP p;
     const double* beta;
-    const int* reset;  // per right-hand side; NULL = never reset
+    const int* emode;
     template <class Real>
     __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const {
+        const int m = emode ? emode[rhs] : 0;
+        if (m == 2) {
+            p.load(rhs, i, s, v);
+            return;
+        }
         r.load(rhs, i, s, v);
-        if (!(reset && reset[rhs])) {
+        if (m == 0) {
             Real b = (Real)beta[rhs];
             Real q[24];
             p.load(rhs, i, s, q);

@@ -84,10 +84,11 @@ __global__ void k_convert(FA a, FB b, long n) {
 }
 
 template <class F>
-__global__ void k_zero(F f, long n) {
+__global__ void k_zero(F f, long n, const int* mask) {
     long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
     int rhs = blockIdx.y;
     if (i >= n) return;
+    if (mask && !mask[rhs]) return;
     double v[24];
 #pragma unroll
     for (int k = 0; k < 24; ++k) v[k] = 0;
@@ -167,10 +168,12 @@ __global__ void k_pack_links(const double* __restrict__ gauge, Dims d, int par, 
     }
 }
 
-__global__ void k_finish(const double* __restrict__ partials, int nblocks, int nrhs, CgState st, int mode) {
+__global__ void k_finish(const double* __restrict__ partials, int nblocks, int nrhs, CgState st, int mode,
+                         const int* __restrict__ mask) {
     __shared__ double red[16];
     for (int r = 0; r < nrhs; ++r) {
         if ((mode == FIN_ALPHA || mode == FIN_BETA) && !st.live[r]) continue;
+        if ((mode == FIN_AUX || mode == FIN_OUTER) && mask && !mask[r]) continue;
         double s = 0;
         for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += partials[(long)r * nblocks + i];
         double tot = block_sum(s, red);
@@ -182,6 +185,7 @@ __global__ void k_finish(const double* __restrict__ partials, int nblocks, int n
                 st.rr[r] = tot;
             } else if (mode == FIN_ALPHA) {
                 st.uu[r] = tot;
+                st.emode[r] = 0;  // kernel E of this iteration has consumed it
                 if (!(tot > 0.0) || !isfinite(tot)) {
                     st.status[r] = 2;
                     st.live[r] = 0;
@@ -215,31 +219,34 @@ __global__ void k_finish(const double* __restrict__ partials, int nblocks, int n
 
 }  // namespace
 
-hipError_t launch_finish(const double* partials, int nblocks, int nrhs, CgState st, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partials, nblocks, nrhs, st, mode);
+hipError_t launch_finish(const double* partials, int nblocks, int nrhs, CgState st, int mode, hipStream_t s,
+                         const int* mask) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partials, nblocks, nrhs, st, mode, mask);
     return hipGetLastError();
 }
 
 hipError_t host_to_half(const dwf_ctx* c, const double* host, int nrhs, HalfField& even, HalfField& odd,
-                        hipStream_t s) {
+                        hipStream_t s, int rhs0) {
     Dims d = dims_of(c);
     dim3 grid((unsigned)((d.V5 + TPB - 1) / TPB), nrhs);
+    const int r0 = rhs0;
     switch (even.prec) {
-        case DWF_PREC_FP64: hipLaunchKernelGGL(k_host_to_half<FD>, grid, dim3(TPB), 0, s, host, d, even.fd(), odd.fd()); break;
-        case DWF_PREC_FP32: hipLaunchKernelGGL(k_host_to_half<FS>, grid, dim3(TPB), 0, s, host, d, even.fs(), odd.fs()); break;
-        default: hipLaunchKernelGGL(k_host_to_half<FH>, grid, dim3(TPB), 0, s, host, d, even.fh(), odd.fh()); break;
+        case DWF_PREC_FP64: hipLaunchKernelGGL(k_host_to_half<FD>, grid, dim3(TPB), 0, s, host, d, even.fd(r0), odd.fd(r0)); break;
+        case DWF_PREC_FP32: hipLaunchKernelGGL(k_host_to_half<FS>, grid, dim3(TPB), 0, s, host, d, even.fs(r0), odd.fs(r0)); break;
+        default: hipLaunchKernelGGL(k_host_to_half<FH>, grid, dim3(TPB), 0, s, host, d, even.fh(r0), odd.fh(r0)); break;
     }
     return hipGetLastError();
 }
 
 hipError_t half_to_host(const dwf_ctx* c, const HalfField& even, const HalfField& odd, int nrhs, double* host,
-                        hipStream_t s) {
+                        hipStream_t s, int rhs0) {
     Dims d = dims_of(c);
     dim3 grid((unsigned)((d.V5 + TPB - 1) / TPB), nrhs);
+    const int r0 = rhs0;
     switch (even.prec) {
-        case DWF_PREC_FP64: hipLaunchKernelGGL(k_half_to_host<FD>, grid, dim3(TPB), 0, s, host, d, even.fd(), odd.fd()); break;
-        case DWF_PREC_FP32: hipLaunchKernelGGL(k_half_to_host<FS>, grid, dim3(TPB), 0, s, host, d, even.fs(), odd.fs()); break;
-        default: hipLaunchKernelGGL(k_half_to_host<FH>, grid, dim3(TPB), 0, s, host, d, even.fh(), odd.fh()); break;
+        case DWF_PREC_FP64: hipLaunchKernelGGL(k_half_to_host<FD>, grid, dim3(TPB), 0, s, host, d, even.fd(r0), odd.fd(r0)); break;
+        case DWF_PREC_FP32: hipLaunchKernelGGL(k_half_to_host<FS>, grid, dim3(TPB), 0, s, host, d, even.fs(r0), odd.fs(r0)); break;
+        default: hipLaunchKernelGGL(k_half_to_host<FH>, grid, dim3(TPB), 0, s, host, d, even.fh(r0), odd.fh(r0)); break;
     }
     return hipGetLastError();
 }
@@ -264,13 +271,13 @@ hipError_t half_convert(const dwf_ctx* c, const HalfField& src, HalfField& dst, 
     }
 }
 
-hipError_t half_zero(const dwf_ctx* c, HalfField& f, int nrhs, hipStream_t s) {
+hipError_t half_zero(const dwf_ctx* c, HalfField& f, int nrhs, hipStream_t s, const int* mask) {
     long n = c->V5h;
     dim3 grid((unsigned)((n + TPB - 1) / TPB), nrhs);
     switch (f.prec) {
-        case DWF_PREC_FP64: hipLaunchKernelGGL(k_zero<FD>, grid, dim3(TPB), 0, s, f.fd(), n); break;
-        case DWF_PREC_FP32: hipLaunchKernelGGL(k_zero<FS>, grid, dim3(TPB), 0, s, f.fs(), n); break;
-        default: hipLaunchKernelGGL(k_zero<FH>, grid, dim3(TPB), 0, s, f.fh(), n); break;
+        case DWF_PREC_FP64: hipLaunchKernelGGL(k_zero<FD>, grid, dim3(TPB), 0, s, f.fd(), n, mask); break;
+        case DWF_PREC_FP32: hipLaunchKernelGGL(k_zero<FS>, grid, dim3(TPB), 0, s, f.fs(), n, mask); break;
+        default: hipLaunchKernelGGL(k_zero<FH>, grid, dim3(TPB), 0, s, f.fh(), n, mask); break;
     }
     return hipGetLastError();
 }

@@ -19,6 +19,14 @@
 // alpha, beta and the convergence flags never leave the device; the host
 // replays a captured hipGraph of several iterations and reads the state back
 // between replays.
+//
+// The engine runs K right-hand sides ("slots") through these kernels at once:
+// every kernel reads each gauge link once for all live slots.  Each slot has
+// its own phase (setup, outer step, inner iterations, reconstruction, done),
+// its own quark mass (its row of the fifth-dimension tables) and its own
+// tolerances, so one slot can restart, finish or be replaced while the others
+// keep iterating.  dwf_solve fills all slots at once; the request server
+// admits and retires slots as requests come and go.
 #include <math.h>
 #include <string.h>
 
@@ -34,10 +42,6 @@ namespace dwf {
 
 template <class F>
 F fld(const HalfField& h);
-template <class Real>
-const Real* tab(const TableSet* ts, int t, int Ns);
-template <class Real>
-const Real* stab(const TableSet* ts, int t, int Ns);
 
 double flops_per_iter(const dwf_ctx* c) {
     return (double)c->V5h * (5280.0 + 192.0 * c->Ns + 288.0);
@@ -52,572 +56,628 @@ double bytes_per_iter(const dwf_ctx* c, int inner_prec, int link_fmt) {
     return (double)c->V5h * (15.0 * sb + 2.0 * yb) + 4.0 * (double)c->V4h * 8.0 * link_bytes(link_fmt);
 }
 
+int link_format(const dwf_solve_params& p) {
+    switch (p.inner_prec) {
+        case DWF_PREC_FP64: return LINK_D18;
+        case DWF_PREC_FP32: return p.link_compress == 1 ? LINK_S12 : LINK_S18;
+        default: return LINK_H12;
+    }
+}
+
 namespace {
 
+// half fields of an engine
 enum { B_E = 0, B_O, BP_E, BP_O, BPP, YH_E, YH_O, T64_E, NF64 };
 enum { L_R = NF64, L_P, L_U, L_T1, L_T23, L_Y, NFALL };
+// per-slot masks on the device (each has its own pinned staging row)
+enum { M_SETUP = 0, M_GUESS, M_NOGUESS, M_OUTER, M_REVERT, M_RUFIN, M_POST, M_FINAL, M_AGAIN, NMASK };
 
-struct HostState {
-    std::vector<double> rr, aux;
-    std::vector<int> live, iters, status;
+constexpr int kItersPerGraph = 4;
+
+long field_elems(long V5h, int prec) {
+    const int nblk = prec == DWF_PREC_FP64 ? 12 : prec == DWF_PREC_FP32 ? 6 : 3;
+    return ((V5h * nblk + 255) / 256) * 256;
+}
+
+// host control state of one slot
+struct SlotCtl {
+    int phase = PH_FREE;
+    dwf_solve_params p{};
+    double mq = 0;
+    int use_guess = 0;
+    int mode_ru = 1, cycles = 0, fellback = 0, noprog = 0, ru_restarts = 0, have_backup = 0, reverted = 0;
+    int failed = 0, round = 0, restarts = 0, stuck = 0;
+    double rhat_prev = 0, tol_schur = 0, true_res = 0, schur_res = 0, bnorm2 = 0, bpp2 = 0;
+    double eps_dc = 0, eps_ru = 0;
+    // convergence-rate bookkeeping for the replay count
+    double rr_last = -1, rate = 0;
+    int it_last = 0, probe = 1;
+    std::chrono::steady_clock::time_point t0;
+    double seconds = 0;
 };
 
 template <class Real, class F, class FY, class LF>
-struct Solver {
+class Engine : public EngineBase {
+  public:
+    Engine(dwf_ctx* c_, int prec_, int fmt_, int K_, hipStream_t s_, LF e, LF o)
+        : c(c_), prec(prec_), link_fmt(fmt_), K(K_), s(s_), lk{e, o},
+          lk64{LinkD18{c_->links[0][LINK_D18].as<double>()}, LinkD18{c_->links[1][LINK_D18].as<double>()}},
+          sl((size_t)K_) {}
+    ~Engine() override {
+        if (pin) (void)hipHostFree(pin);
+    }
+
+    int init() {
+        int rc;
+        std::vector<int> precs(NF64, DWF_PREC_FP64);
+        for (int i = 0; i < 5; ++i) precs.push_back(prec);
+        precs.push_back(prec == DWF_PREC_FP64 ? DWF_PREC_FP64 : DWF_PREC_FP32);  // y
+        if ((rc = w.alloc(precs, c->V5h, c->Ns, K)) || (rc = w.alloc_state(K))) return rc;
+        TS = (long)tables_size(c->Ns);
+        if ((rc = tabs64.alloc((size_t)TS * K * sizeof(double))) || (rc = tabs32.alloc((size_t)TS * K * sizeof(float))))
+            return rc;
+        nbmax = std::max(c->geom(0, true).nblocks, c->geom(0, false).nblocks);
+        if ((rc = aux.alloc((size_t)nbmax * K * sizeof(double) + (size_t)NMASK * K * sizeof(int)))) return rc;
+        for (int m = 0; m < NMASK; ++m) dmask[m] = (int*)(aux.as<double>() + (size_t)nbmax * K) + (size_t)m * K;
+        DWF_HIP(hipMemset(aux.p, 0, aux.bytes));
+        const size_t bytes = 6 * (size_t)K * sizeof(double) + (5 + NMASK) * (size_t)K * sizeof(int);
+        DWF_HIP(hipHostMalloc(&pin, bytes, hipHostMallocDefault));
+        memset(pin, 0, bytes);
+        hd = (double*)pin;
+        hi = (int*)(hd + 6 * (size_t)K);
+        for (int m = 0; m < NMASK; ++m) hmask[m] = hi + 5 * (size_t)K + (size_t)m * K;
+        return DWF_OK;
+    }
+
+    int capacity() const override { return K; }
+    int phase(int r) const override { return sl[r].phase; }
+    int busy() const override {
+        int n = 0;
+        for (auto& x : sl) n += x.phase != PH_FREE;
+        return n;
+    }
+    int pending() const override {
+        int n = 0;
+        for (auto& x : sl) n += x.phase != PH_FREE && x.phase != PH_DONE;
+        return n;
+    }
+    void set_stream(hipStream_t st) override { s = st; }
+    void set_use_graph(bool on) override { use_graph = on; }
+    void set_replay_cap(int n) override { replay_cap = std::max(1, n); }
+    size_t device_bytes() const override {
+        size_t b = w.state.bytes + tabs64.bytes + tabs32.bytes + aux.bytes;
+        for (auto& f : w.fields) b += f->data.bytes + f->nrm.bytes;
+        return b;
+    }
+
+    int admit(int r, const double* b_dev, const double* x0_dev, double mq, const dwf_solve_params& p) override {
+        if (r < 0 || r >= K || sl[r].phase != PH_FREE) return fail(DWF_EINVAL, "slot not free");
+        int rc;
+        const TableSet* ts = c->table_set(mq, &rc);
+        if (!ts) return rc;
+        DWF_HIP(hipMemcpyAsync(tabs64.as<double>() + (size_t)r * TS, ts->d64.p, TS * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+        DWF_HIP(hipMemcpyAsync(tabs32.as<float>() + (size_t)r * TS, ts->d32.p, TS * sizeof(float),
+                               hipMemcpyDeviceToDevice, s));
+        DWF_HIP(host_to_half(c, b_dev, 1, w.f(B_E), w.f(B_O), s, r));
+        if (x0_dev) DWF_HIP(host_to_half(c, x0_dev, 1, w.f(BP_E), w.f(BP_O), s, r));
+        SlotCtl& q = sl[r];
+        q = SlotCtl{};
+        q.phase = PH_SETUP;
+        q.p = p;
+        q.mq = mq;
+        q.use_guess = x0_dev != nullptr;
+        q.mode_ru = p.reliable ? 1 : 0;
+        q.tol_schur = p.tol;
+        q.eps_dc = p.eps_inner > 0 ? p.eps_inner
+                                   : (prec == DWF_PREC_FP32 ? 1e-5 : prec == DWF_PREC_FP16 ? 2e-3 : 0.0);
+        q.eps_ru = p.eps_inner > 0 ? p.eps_inner : (prec == DWF_PREC_FP64 ? 0.0 : 0.1);
+        q.t0 = std::chrono::steady_clock::now();
+        return DWF_OK;
+    }
+
+    int tick() override {
+        int rc;
+        if (any(PH_SETUP) && (rc = setup())) return rc;
+        for (int guard = 0; any(PH_OUTER) || any(PH_FINAL); ++guard) {
+            if (guard > 64) return fail(DWF_EDEVICE, "solve engine: outer loop does not settle");
+            if (any(PH_OUTER) && (rc = outer())) return rc;
+            if (any(PH_FINAL) && (rc = final_check())) return rc;
+        }
+        if (any(PH_INNER) && (rc = inner())) return rc;
+        return DWF_OK;
+    }
+
+    int retire(int r, double* x_dev, SlotResult* res) override {
+        if (r < 0 || r >= K || sl[r].phase != PH_DONE) return fail(DWF_EINVAL, "slot not done");
+        SlotCtl& q = sl[r];
+        if (x_dev) DWF_HIP(half_to_host(c, w.f(BP_E), w.f(BP_O), 1, x_dev, s, r));
+        if (res) {
+            const double V = (double)c->V5h;
+            const double fo = V * (2640.0 + 96.0 * c->Ns + 72.0);
+            const double fsetup = V * (144.0 * c->Ns + 1392.0);
+            const double ffinal = V * (336.0 * c->Ns + 4080.0);
+            res->status = (!q.failed && q.true_res <= q.p.tol) ? DWF_OK : DWF_ENOCONV;
+            res->iters = hi[K + r];
+            res->restarts = q.restarts;
+            res->reliable_updates = q.ru_restarts;
+            res->fallback = q.fellback;
+            res->true_residual = q.true_res;
+            res->schur_residual = q.schur_res;
+            res->seconds = q.seconds;
+            res->flops = flops_per_iter(c) * res->iters + fo * q.restarts + fsetup + ffinal * (q.round + 1);
+            res->bytes = bytes_per_iter(c, prec, link_fmt) * res->iters + 12.0 * V * 192.0 * (q.restarts + 4);
+        }
+        q.phase = PH_FREE;
+        return DWF_OK;
+    }
+
+    int time_kernels(int launches, double* ms, double* bytes) override;
+
+  private:
     dwf_ctx* c;
-    const TableSet* ts;
-    Workspace* w;
+    int prec, link_fmt, K;
+    hipStream_t s;
     LF lk[2];
     LinkD18 lk64[2];
-    int nrhs;
-    hipStream_t s;
-    DevBuf* partials;
-    int* mask_a;  // device int[nrhs]
-    int* mask_b;
-    const dwf_solve_params& p;
+    std::vector<SlotCtl> sl;
+    Workspace w;
+    DevBuf tabs64, tabs32, aux;
+    long TS = 0;
+    int nbmax = 0;
+    int* dmask[NMASK] = {};
+    void* pin = nullptr;
+    double* hd = nullptr;  // rr, uu, alpha, beta, rr_target, aux  (K each)
+    int* hi = nullptr;     // live, iters, status, maxiter, emode   (K each), then the masks
+    int* hmask[NMASK] = {};
+    bool use_graph = true;
+    int replays = 1, replay_cap = 64;
 
+    // host mirrors
+    double& h_rr(int r) { return hd[r]; }
+    double& h_target(int r) { return hd[4 * K + r]; }
+    double& h_aux(int r) { return hd[5 * K + r]; }
+    int& h_live(int r) { return hi[r]; }
+    int& h_iters(int r) { return hi[K + r]; }
+    int& h_status(int r) { return hi[2 * K + r]; }
+    int& h_maxiter(int r) { return hi[3 * K + r]; }
+    int& h_emode(int r) { return hi[4 * K + r]; }
+
+    bool any(int ph) const {
+        for (auto& x : sl)
+            if (x.phase == ph) return true;
+        return false;
+    }
+
+    // ---------------- device state transfers ----------------
+    // The host writes a mirror only after a pull (the stream is idle then) and
+    // pushes it before the next pull, so the mirrors never race an async copy.
+    int pull() {
+        DWF_HIP(hipMemcpyAsync(hd, w.st.rr, 6 * (size_t)K * sizeof(double), hipMemcpyDeviceToHost, s));
+        DWF_HIP(hipMemcpyAsync(hi, w.st.live, 5 * (size_t)K * sizeof(int), hipMemcpyDeviceToHost, s));
+        DWF_HIP(hipStreamSynchronize(s));
+        return DWF_OK;
+    }
+    int push_ctl() {
+        DWF_HIP(hipMemcpyAsync(w.st.rr_target, &h_target(0), (size_t)K * sizeof(double), hipMemcpyHostToDevice, s));
+        DWF_HIP(hipMemcpyAsync(w.st.live, hi, 5 * (size_t)K * sizeof(int), hipMemcpyHostToDevice, s));
+        return DWF_OK;
+    }
+    template <class Pred>
+    int upload_mask(int m, Pred pred) {
+        int n = 0;
+        for (int r = 0; r < K; ++r) n += (hmask[m][r] = pred(r) ? 1 : 0);
+        DWF_HIP(hipMemcpyAsync(dmask[m], hmask[m], (size_t)K * sizeof(int), hipMemcpyHostToDevice, s));
+        return n;
+    }
+
+    // ---------------- kernels ----------------
     Geom g64(int par) const { return c->geom(par, true); }
     Geom glo(int par) const { return c->geom(par, sizeof(Real) == 8); }
-    FD d(int i) const { return w->f(i).fd(); }
-    F lo(int i) const { return fld<F>(w->f(i)); }
-    FY ylo() const { return fld<FY>(w->f(L_Y)); }
-    const double* t64(int t) const { return tab<double>(ts, t, c->Ns); }
-    const Real* tlo(int t) const { return tab<Real>(ts, t, c->Ns); }
-    const double* s64(int t) const { return stab<double>(ts, t, c->Ns); }
-    const Real* slo(int t) const { return stab<Real>(ts, t, c->Ns); }
-    double* part() const { return partials->as<double>(); }
-    KOpt kopt(const int* live, bool red) const { return KOpt{live, red ? part() : nullptr, nrhs, 0}; }
-
-    // ---------------- FP64 pieces ----------------
-    hipError_t local64(int par, int in, int table, int out) {
-        return launch_dwf<double, FD, LinkD18, false, MIX_DENSE, ProLoad<FD>, EpiStore<FD>>(
-            g64(par), d(in), lk64[par], t64(table), ProLoad<FD>{d(in)}, EpiStore<FD>{d(out)}, kopt(nullptr, false), s);
+    FD d(int i) { return w.f(i).fd(); }
+    F lo(int i) { return fld<F>(w.f(i)); }
+    FY ylo() { return fld<FY>(w.f(L_Y)); }
+    const double* t64(int t) const { return tabs64.as<double>() + dense_table_offset(c->Ns, t); }
+    const double* s64(int t) const { return tabs64.as<double>() + struct_table_offset(c->Ns, t); }
+    const Real* slo(int t) const {
+        if constexpr (sizeof(Real) == 8)
+            return tabs64.as<double>() + struct_table_offset(c->Ns, t);
+        else
+            return tabs32.as<float>() + struct_table_offset(c->Ns, t);
     }
-    hipError_t norm64(int par, int in) {
+    double* part() const { return aux.as<double>(); }
+    KOpt kopt(const int* live, bool red) const { return KOpt{live, red ? part() : nullptr, K, TS}; }
+    hipError_t fin(int nblocks, int mode, const int* mask = nullptr) {
+        return launch_finish(part(), nblocks, K, w.st, mode, s, mask);
+    }
+
+    hipError_t local64(int par, int in, int table, int out, const int* m) {
+        return launch_dwf<double, FD, LinkD18, false, MIX_DENSE, ProLoad<FD>, EpiStore<FD>>(
+            g64(par), d(in), lk64[par], t64(table), ProLoad<FD>{d(in)}, EpiStore<FD>{d(out)}, kopt(m, false), s);
+    }
+    hipError_t norm64(int par, int in, const int* m) {
         return launch_dwf<double, FD, LinkD18, false, MIX_NONE, ProLoad<FD>, EpiNorm>(
-            g64(par), d(in), lk64[par], nullptr, ProLoad<FD>{d(in)}, EpiNorm{}, kopt(nullptr, true), s);
+            g64(par), d(in), lk64[par], nullptr, ProLoad<FD>{d(in)}, EpiNorm{}, kopt(m, true), s);
     }
     // out = a - M5 D^{par,1-par} in
-    hipError_t xmy_m5hop64(int par, int in, int a, int out, bool red) {
+    hipError_t xmy_m5hop64(int par, int in, int a, int out, bool red, const int* m) {
         if (red)
             return launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiLin<FD, FD, true, false>>(
                 g64(par), d(in), lk64[par], s64(ST_M5), ProLoad<FD>{d(in)},
-                EpiLin<FD, FD, true, false>{d(a), d(out), 1.0, -1.0}, kopt(nullptr, true), s);
+                EpiLin<FD, FD, true, false>{d(a), d(out), 1.0, -1.0}, kopt(m, true), s);
         return launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiLin<FD, FD, false, false>>(
             g64(par), d(in), lk64[par], s64(ST_M5), ProLoad<FD>{d(in)},
-            EpiLin<FD, FD, false, false>{d(a), d(out), 1.0, -1.0}, kopt(nullptr, false), s);
+            EpiLin<FD, FD, false, false>{d(a), d(out), 1.0, -1.0}, kopt(m, false), s);
     }
-    hipError_t fin(int nblocks, int mode) { return launch_finish(part(), nblocks, nrhs, w->st, mode, s); }
-
-    // rhat = b'' - C yhat_o  (FP64), r_lo = rhat, y_lo = 0, rr = aux = |rhat|^2
-    hipError_t outer_residual() {
+    // rhat = b'' - C yhat_o (FP64), r_lo = rhat, y_lo = 0, rr = aux = |rhat|^2
+    hipError_t outer_residual(const int* m) {
         hipError_t e = launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiStore<FD>>(
-            g64(0), d(YH_O), lk64[0], s64(ST_M5), ProLoad<FD>{d(YH_O)}, EpiStore<FD>{d(T64_E)}, kopt(nullptr, false), s);
+            g64(0), d(YH_O), lk64[0], s64(ST_M5), ProLoad<FD>{d(YH_O)}, EpiStore<FD>{d(T64_E)}, kopt(m, false), s);
         if (e != hipSuccess) return e;
         e = launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiOuter<FD, FD, F, FY>>(
             g64(1), d(T64_E), lk64[1], s64(ST_M5), ProLoad<FD>{d(T64_E)},
-            EpiOuter<FD, FD, F, FY>{d(BPP), d(YH_O), lo(L_R), ylo()}, kopt(nullptr, true), s);
+            EpiOuter<FD, FD, F, FY>{d(BPP), d(YH_O), lo(L_R), ylo()}, kopt(m, true), s);
         if (e != hipSuccess) return e;
-        return fin(g64(1).nblocks, FIN_OUTER);
+        return fin(g64(1).nblocks, FIN_OUTER, m);
+    }
+    // res = b - D x on one parity, |res|^2 into the block sums; yx = (Y x) of
+    // the other parity, xx = X x of this one
+    hipError_t true_res(int par, int yx, int b, int xx, const int* m) {
+        return launch_dwf<double, FD, LinkD18, true, MIX_NONE, ProLoad<FD>, EpiTrueRes<FD, FD>>(
+            g64(par), d(yx), lk64[par], nullptr, ProLoad<FD>{d(yx)}, EpiTrueRes<FD, FD>{d(b), d(xx)}, kopt(m, true), s);
     }
 
-    // ---------------- inner CG kernels ----------------
-    hipError_t kE(const int* live, const int* reset) {
+    // inner CG kernels
+    hipError_t kE(const int* live, const int* emode) {
         return launch_dwf<Real, F, LF, false, MIX_AS, ProCgE<F, F>, EpiStore<F>>(
-            glo(1), lo(L_R), lk[1], slo(ST_M5TG5), ProCgE<F, F>{lo(L_R), lo(L_P), w->st.beta, reset},
+            glo(1), lo(L_R), lk[1], slo(ST_M5TG5), ProCgE<F, F>{lo(L_R), lo(L_P), w.st.beta, emode},
             EpiStore<F>{lo(L_T1)}, kopt(live, false), s);
     }
-    hipError_t kA() {
+    hipError_t kA(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_AS, ProLoad<F>, EpiStore<F>>(
-            glo(0), lo(L_T1), lk[0], slo(ST_M5T), ProLoad<F>{lo(L_T1)}, EpiStore<F>{lo(L_T23)}, kopt(w->st.live, false),
+            glo(0), lo(L_T1), lk[0], slo(ST_M5T), ProLoad<F>{lo(L_T1)}, EpiStore<F>{lo(L_T23)}, kopt(live, false), s);
+    }
+    hipError_t kB(const int* live) {
+        return launch_dwf<Real, F, LF, true, MIX_NONE, ProLoad<F>, EpiCgB<F, F>>(
+            glo(1), lo(L_T23), lk[1], nullptr, ProLoad<F>{lo(L_T23)}, EpiCgB<F, F>{lo(L_P), lo(L_U)}, kopt(live, true),
             s);
     }
-    hipError_t kB() {
-        return launch_dwf<Real, F, LF, true, MIX_NONE, ProLoad<F>, EpiCgB<F, F>>(
-            glo(1), lo(L_T23), lk[1], nullptr, ProLoad<F>{lo(L_T23)}, EpiCgB<F, F>{lo(L_P), lo(L_U)},
-            kopt(w->st.live, true), s);
-    }
-    hipError_t kC() {
+    hipError_t kC(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiStore<F>>(
-            glo(0), lo(L_U), lk[0], slo(ST_M5), ProLoad<F>{lo(L_U)}, EpiStore<F>{lo(L_T23)}, kopt(w->st.live, false), s);
+            glo(0), lo(L_U), lk[0], slo(ST_M5), ProLoad<F>{lo(L_U)}, EpiStore<F>{lo(L_T23)}, kopt(live, false), s);
     }
-    hipError_t kD() {
+    hipError_t kD(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiCgD<F, F, FY>>(
             glo(1), lo(L_T23), lk[1], slo(ST_M5), ProLoad<F>{lo(L_T23)},
-            EpiCgD<F, F, FY>{lo(L_U), lo(L_R), ylo(), w->st.alpha}, kopt(w->st.live, true), s);
+            EpiCgD<F, F, FY>{lo(L_U), lo(L_R), ylo(), w.st.alpha}, kopt(live, true), s);
     }
-    hipError_t iteration(bool with_e) {
+    hipError_t iteration() {
         hipError_t e;
-        if (with_e && (e = kE(w->st.live, nullptr)) != hipSuccess) return e;
-        if ((e = kA()) != hipSuccess) return e;
-        if ((e = kB()) != hipSuccess) return e;
+        const int* live = w.st.live;
+        if ((e = kE(live, w.st.emode)) != hipSuccess) return e;
+        if ((e = kA(live)) != hipSuccess) return e;
+        if ((e = kB(live)) != hipSuccess) return e;
         if ((e = fin(glo(1).nblocks, FIN_ALPHA)) != hipSuccess) return e;
-        if ((e = kC()) != hipSuccess) return e;
-        if ((e = kD()) != hipSuccess) return e;
+        if ((e = kC(live)) != hipSuccess) return e;
+        if ((e = kD(live)) != hipSuccess) return e;
         return fin(glo(1).nblocks, FIN_BETA);
     }
-
-    int ensure_graph(int iters_per_graph) {
-        if (w->gexec && w->graph_iters == iters_per_graph) return DWF_OK;
-        if (w->gexec) (void)hipGraphExecDestroy(w->gexec);
-        if (w->graph) (void)hipGraphDestroy(w->graph);
-        w->gexec = nullptr;
-        w->graph = nullptr;
+    int ensure_graph() {
+        if (w.gexec) return DWF_OK;
         DWF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
-        for (int i = 0; i < iters_per_graph && e == hipSuccess; ++i) e = iteration(true);
+        for (int i = 0; i < kItersPerGraph && e == hipSuccess; ++i) e = iteration();
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(s, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             return fail(DWF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
         }
-        w->graph = g;
-        DWF_HIP(hipGraphInstantiate(&w->gexec, g, nullptr, nullptr, 0));
-        w->graph_iters = iters_per_graph;
+        w.graph = g;
+        DWF_HIP(hipGraphInstantiate(&w.gexec, g, nullptr, nullptr, 0));
+        w.graph_iters = kItersPerGraph;
         return DWF_OK;
     }
-};
 
-template <class Real, class F, class FY, class LF>
-int run_solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params& p,
-              dwf_solve_stats* stats, hipStream_t s, int link_fmt, LF lke, LF lko) {
-    int rc;
-    const TableSet* ts = c->table_set(c->mq, &rc);
-    if (!ts) return rc;
-    const int prec = p.inner_prec;
-    std::string key = "solve:" + std::to_string(prec) + ":" + std::to_string(link_fmt) + ":" + std::to_string(nrhs);
-    auto& slot = c->ws[key];
-    if (!slot) {
-        slot.reset(new Workspace);
-        std::vector<int> precs(NF64, DWF_PREC_FP64);
-        for (int i = 0; i < 5; ++i) precs.push_back(prec);
-        precs.push_back(prec == DWF_PREC_FP64 ? DWF_PREC_FP64 : DWF_PREC_FP32);  // y
-        if ((rc = slot->alloc(precs, c->V5h, c->Ns, nrhs)) || (rc = slot->alloc_state(nrhs))) {
-            slot.reset();
-            return rc;
-        }
-    }
-    Workspace* w = slot.get();
-    // per-workspace block sums and masks (fixed addresses: the graph keeps them)
-    auto& pslot = c->ws[key + ":aux"];
-    if (!pslot) {
-        pslot.reset(new Workspace);
-        long nb = std::max(c->geom(0, true).nblocks, c->geom(0, false).nblocks);
-        if ((rc = pslot->state.alloc((size_t)nb * nrhs * sizeof(double) + 2 * (size_t)nrhs * sizeof(int)))) {
-            pslot.reset();
-            return rc;
-        }
-    }
-    DevBuf* partials_buf = &pslot->state;
-    long nbmax = std::max(c->geom(0, true).nblocks, c->geom(0, false).nblocks);
-    int* mask_a = (int*)(partials_buf->as<double>() + nbmax * nrhs);
-    int* mask_b = mask_a + nrhs;
-
-    Solver<Real, F, FY, LF> S{c, ts, w, {lke, lko},
-                              {LinkD18{c->links[0][LINK_D18].as<double>()}, LinkD18{c->links[1][LINK_D18].as<double>()}},
-                              nrhs, s, partials_buf, mask_a, mask_b, p};
-
-    // pinned host mirrors of the device state
-    struct Pinned {
-        void* p = nullptr;
-        ~Pinned() { if (p) (void)hipHostFree(p); }
-    } pin;
-    const size_t nd = 6 * (size_t)nrhs, ni = 4 * (size_t)nrhs;
-    DWF_HIP(hipHostMalloc(&pin.p, nd * sizeof(double) + ni * sizeof(int) + 2 * nrhs * sizeof(int), hipHostMallocDefault));
-    double* hd = (double*)pin.p;
-    int* hi = (int*)(hd + nd);
-    double* h_rr = hd;
-    double* h_target = hd + 4 * nrhs;
-    double* h_aux = hd + 5 * nrhs;
-    int* h_live = hi;
-    int* h_iters = hi + nrhs;
-    int* h_status = hi + 2 * nrhs;
-    int* h_maxiter = hi + 3 * nrhs;
-    int* h_mask = hi + 4 * nrhs;  // 2 * nrhs
-    const CgState& st = w->st;
-
-    auto pull = [&]() -> int {
-        DWF_HIP(hipMemcpyAsync(hd, st.rr, nd * sizeof(double), hipMemcpyDeviceToHost, s));
-        DWF_HIP(hipMemcpyAsync(hi, st.live, ni * sizeof(int), hipMemcpyDeviceToHost, s));
-        DWF_HIP(hipStreamSynchronize(s));
-        return DWF_OK;
-    };
-    auto push_ctl = [&]() -> int {
-        DWF_HIP(hipMemcpyAsync(st.rr_target, h_target, nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-        DWF_HIP(hipMemcpyAsync(st.live, h_live, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-        DWF_HIP(hipMemcpyAsync(st.maxiter, h_maxiter, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-        DWF_HIP(hipMemcpyAsync(st.status, h_status, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-        DWF_HIP(hipMemcpyAsync(mask_a, h_mask, 2 * nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-        return DWF_OK;
-    };
-#define CKE(x)                                                                                  \
-    do {                                                                                        \
-        hipError_t e_ = (x);                                                                    \
+#define CKE(x)                                                                                          \
+    do {                                                                                                \
+        hipError_t e_ = (x);                                                                            \
         if (e_ != hipSuccess) return fail(DWF_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
-#define CKR(x)          \
-    do {                \
-        int r_ = (x);   \
+#define CKR(x)             \
+    do {                   \
+        int r_ = (x);      \
         if (r_) return r_; \
     } while (0)
 
-    hipEvent_t ev0, ev1;
-    DWF_HIP(hipEventCreate(&ev0));
-    DWF_HIP(hipEventCreate(&ev1));
-    struct EvGuard {
-        hipEvent_t a, b;
-        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-    } evg{ev0, ev1};
-    DWF_HIP(hipEventRecord(ev0, s));
-
-    // reset per-solve state
-    for (int r = 0; r < nrhs; ++r) {
-        h_live[r] = 0;
-        h_status[r] = 0;
-        h_maxiter[r] = p.maxiter;
-        h_target[r] = 0;
-        h_mask[r] = 0;
-        h_mask[nrhs + r] = 0;
+    // ---- b -> |b|^2, b' = S1 b, b'' = b'_o - M5 D^OE b'_e, |b''|^2, initial yhat_o
+    int setup() {
+        int* m = dmask[M_SETUP];
+        upload_mask(M_SETUP, [&](int r) { return sl[r].phase == PH_SETUP; });
+        CKE(norm64(0, B_E, m));
+        CKE(fin(g64(0).nblocks, FIN_AUX, m));
+        CKR(pull());
+        for (int r = 0; r < K; ++r)
+            if (hmask[M_SETUP][r]) sl[r].bnorm2 = h_aux(r);
+        CKE(norm64(1, B_O, m));
+        CKE(fin(g64(1).nblocks, FIN_AUX, m));
+        CKR(pull());
+        for (int r = 0; r < K; ++r)
+            if (hmask[M_SETUP][r]) sl[r].bnorm2 += h_aux(r);
+        int ng = upload_mask(M_GUESS, [&](int r) { return hmask[M_SETUP][r] && sl[r].use_guess; });
+        int nz = upload_mask(M_NOGUESS, [&](int r) { return hmask[M_SETUP][r] && !sl[r].use_guess; });
+        if (ng) CKE(local64(1, BP_O, TB_S2INV, YH_O, dmask[M_GUESS]));
+        if (nz) CKE(half_zero(c, w.f(YH_O), K, s, dmask[M_NOGUESS]));
+        CKE(local64(0, B_E, TB_S1, BP_E, m));
+        CKE(local64(1, B_O, TB_S1, BP_O, m));
+        CKE(xmy_m5hop64(1, BP_E, BP_O, BPP, true, m));
+        CKE(fin(g64(1).nblocks, FIN_AUX, m));
+        CKR(pull());
+        for (int r = 0; r < K; ++r)
+            if (hmask[M_SETUP][r]) {
+                sl[r].bpp2 = h_aux(r);
+                sl[r].phase = PH_OUTER;
+                h_live(r) = 0;
+                h_iters(r) = 0;
+                h_status(r) = 0;
+                h_maxiter(r) = sl[r].p.maxiter;
+                h_emode(r) = 0;
+                h_target(r) = 0;
+            }
+        return push_ctl();
     }
-    DWF_HIP(hipMemsetAsync(st.iters, 0, nrhs * sizeof(int), s));
-    CKR(push_ctl());
 
-    const int nb64o = S.g64(1).nblocks, nb64e = S.g64(0).nblocks;
-
-    // ---- setup: b -> SoA, |b|^2, b' = S1 b, b'' = b'_o - M5 D^OE b'_e, |b''|^2
-    CKE(host_to_half(c, b_dev, nrhs, w->f(B_E), w->f(B_O), s));
-    std::vector<double> bnorm2(nrhs, 0.0), bpp2(nrhs, 0.0);
-    CKE(S.norm64(0, B_E));
-    CKE(S.fin(nb64e, FIN_AUX));
-    CKR(pull());
-    for (int r = 0; r < nrhs; ++r) bnorm2[r] = h_aux[r];
-    CKE(S.norm64(1, B_O));
-    CKE(S.fin(nb64o, FIN_AUX));
-    CKR(pull());
-    for (int r = 0; r < nrhs; ++r) bnorm2[r] += h_aux[r];
-
-    if (p.use_guess) {
-        CKE(host_to_half(c, x_dev, nrhs, w->f(BP_E), w->f(BP_O), s));
-        CKE(S.local64(1, BP_O, TB_S2INV, YH_O));
-    } else {
-        CKE(half_zero(c, w->f(YH_O), nrhs, s));
-    }
-    CKE(S.local64(0, B_E, TB_S1, BP_E));
-    CKE(S.local64(1, B_O, TB_S1, BP_O));
-    CKE(S.xmy_m5hop64(1, BP_E, BP_O, BPP, true));
-    CKE(S.fin(nb64o, FIN_AUX));
-    CKR(pull());
-    for (int r = 0; r < nrhs; ++r) bpp2[r] = h_aux[r];
-
-    // ---- per-rhs control state
-    // Inner relative tolerance per restart.  Defect correction rebuilds the
-    // Krylov space at every restart and can run far (eps_dc).  Reliable updates
-    // keep p, so they restart each time the iterated residual has dropped by
-    // eps_ru, before the low-precision drift between the iterated and the true
-    // residual grows comparable to the residual itself.
-    const double eps_dc = p.eps_inner > 0 ? p.eps_inner
-                                          : (prec == DWF_PREC_FP32 ? 1e-5 : prec == DWF_PREC_FP16 ? 2e-3 : 0.0);
-    const double eps_ru = p.eps_inner > 0 ? p.eps_inner : (prec == DWF_PREC_FP64 ? 0.0 : 0.1);
-    std::vector<int> mode_ru(nrhs, p.reliable ? 1 : 0), cycles(nrhs, 0), fellback(nrhs, 0), done(nrhs, 0),
-        noprog(nrhs, 0), ru_restarts(nrhs, 0), have_backup(nrhs, 0), reverted(nrhs, 0);
-    std::vector<double> rhat_prev(nrhs, 0.0), tol_schur(nrhs, p.tol), true_res(nrhs, 0.0), schur_res(nrhs, 0.0);
-    int restarts = 0;
-    const int iters_per_graph = 4;
-    const bool verbose = getenv("DWF_VERBOSE") != nullptr;
-    if (p.use_graph) CKR(S.ensure_graph(iters_per_graph));
-    bool failed_any = false;
-
-    for (int round = 0; round < 6; ++round) {
-        // ================= outer loop (Algorithm 2 with reliable updates) =================
-        for (int cyc = 0; cyc < 400; ++cyc) {
-            CKE(S.outer_residual());
-            ++restarts;
+    // ---- outer step (Algorithm 2 with reliable updates) for the slots in PH_OUTER
+    int outer() {
+        int* m = dmask[M_OUTER];
+        upload_mask(M_OUTER, [&](int r) { return sl[r].phase == PH_OUTER; });
+        CKE(outer_residual(m));
+        for (int r = 0; r < K; ++r)
+            if (hmask[M_OUTER][r]) {
+                sl[r].restarts++;
+                sl[r].reverted = 0;
+            }
+        CKR(pull());
+        // A cycle that did not lower the true residual is rejected: the
+        // previous iterate (kept in YH_E) is restored, and reliable updates
+        // give way to defect correction (Sec. 2.3's automatic switch).
+        int nrev = upload_mask(M_REVERT, [&](int r) {
+            return hmask[M_OUTER][r] && sl[r].have_backup && !(sqrt(h_aux(r)) < sl[r].rhat_prev);
+        });
+        if (nrev) {
+            CKE(half_copy(c, w.f(YH_O), w.f(YH_E), K, dmask[M_REVERT], s));
+            CKE(outer_residual(dmask[M_REVERT]));
             CKR(pull());
-            // A cycle that did not lower the true residual is rejected: the
-            // previous iterate (kept in YH_E) is restored, and reliable updates
-            // give way to defect correction (Sec. 2.3's automatic switch).
-            bool revert = false;
-            for (int r = 0; r < nrhs; ++r) {
-                reverted[r] = 0;
-                h_mask[r] = (!done[r] && have_backup[r] && !(sqrt(h_aux[r]) < rhat_prev[r])) ? 1 : 0;
-                revert |= h_mask[r] != 0;
-            }
-            if (revert) {
-                DWF_HIP(hipMemcpyAsync(mask_a, h_mask, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-                CKE(half_copy(c, w->f(YH_O), w->f(YH_E), nrhs, mask_a, s));
-                CKE(S.outer_residual());
-                ++restarts;
-                CKR(pull());
-                for (int r = 0; r < nrhs; ++r)
-                    if (h_mask[r]) {
-                        reverted[r] = 1;
-                        if (mode_ru[r]) {
-                            mode_ru[r] = 0;
-                            fellback[r] = 1;
-                        } else if (++noprog[r] >= 4) {  // defect correction no longer converges
-                            done[r] = 1;
-                            failed_any = true;
-                        }
+            for (int r = 0; r < K; ++r)
+                if (hmask[M_REVERT][r]) {
+                    SlotCtl& q = sl[r];
+                    q.restarts++;
+                    q.reverted = 1;
+                    if (q.mode_ru) {
+                        q.mode_ru = 0;
+                        q.fellback = 1;
+                    } else if (++q.noprog >= 4) {  // defect correction no longer converges
+                        q.failed = 1;
                     }
-            }
-            bool any = false;
-            for (int r = 0; r < nrhs; ++r) {
-                double rh2 = h_aux[r];
-                double rel = bpp2[r] > 0 ? sqrt(rh2 / bpp2[r]) : 0.0;
-                schur_res[r] = rel;
-                h_mask[r] = 0;           // mask_a: reset p := r (defect correction / first cycle)
-                h_mask[nrhs + r] = 0;    // mask_b: continuing with p kept
-                if (done[r] || !(rel > tol_schur[r]) || !std::isfinite(rh2)) {
-                    if (!std::isfinite(rh2)) failed_any = true;
-                    done[r] = 1;
-                    h_live[r] = 0;
-                    continue;
                 }
-                if (cycles[r] > 0 && !reverted[r]) {
-                    if (mode_ru[r]) {
-                        // reliable-update stall test
-                        bool stalled = sqrt(rh2) > 0.5 * rhat_prev[r] || h_status[r] == 2 || h_status[r] == 4 ||
-                                       (p.debug_stall_after > 0 && ru_restarts[r] >= p.debug_stall_after);
-                        if (stalled) {
-                            mode_ru[r] = 0;
-                            fellback[r] = 1;
-                        } else {
-                            ++ru_restarts[r];
-                        }
-                    } else if (sqrt(rh2) > 0.9 * rhat_prev[r]) {
-                        if (++noprog[r] >= 4) {
-                            done[r] = 1;
-                            failed_any = true;
-                            h_live[r] = 0;
-                            continue;
-                        }
+        }
+        for (int r = 0; r < K; ++r) {
+            if (!hmask[M_OUTER][r]) continue;
+            SlotCtl& q = sl[r];
+            const double rh2 = h_aux(r);
+            const double rel = q.bpp2 > 0 ? sqrt(rh2 / q.bpp2) : 0.0;
+            q.schur_res = rel;
+            h_live(r) = 0;
+            if (q.failed || !(rel > q.tol_schur) || !std::isfinite(rh2)) {
+                if (!std::isfinite(rh2)) q.failed = 1;
+                q.phase = PH_FINAL;
+                continue;
+            }
+            if (q.cycles > 0 && !q.reverted) {
+                if (q.mode_ru) {
+                    // reliable-update stall test
+                    const int st = h_status(r);
+                    bool stalled = sqrt(rh2) > 0.5 * q.rhat_prev || st == 2 || st == 4 ||
+                                   (q.p.debug_stall_after > 0 && q.ru_restarts >= q.p.debug_stall_after);
+                    if (stalled) {
+                        q.mode_ru = 0;
+                        q.fellback = 1;
                     } else {
-                        noprog[r] = 0;
+                        ++q.ru_restarts;
                     }
-                }
-                rhat_prev[r] = sqrt(rh2);
-                const double eps = mode_ru[r] ? eps_ru : eps_dc;
-                double stop = 0.5 * tol_schur[r] * sqrt(bpp2[r]);
-                double tgt = std::max(eps * sqrt(rh2), stop);
-                h_target[r] = tgt * tgt;
-                h_live[r] = 1;
-                h_status[r] = 0;
-                if (cycles[r] == 0 || !mode_ru[r] || reverted[r])
-                    h_mask[r] = 1;
-                else
-                    h_mask[nrhs + r] = 1;
-                ++cycles[r];
-                any = true;
-            }
-            for (int r = 0; r < nrhs; ++r) h_maxiter[r] = p.maxiter;
-            if (verbose)
-                for (int r = 0; r < nrhs; ++r)
-                    fprintf(stderr, "[dwf] round %d cycle %d rhs %d: |rhat|/|b''| = %.3e  mode=%s iters=%d live=%d%s\n",
-                            round, cyc, r, schur_res[r], mode_ru[r] ? "RU" : "DC", h_iters[r], h_live[r],
-                            reverted[r] ? " (reverted)" : "");
-            if (!any) break;
-            // iteration cap over all cycles
-            for (int r = 0; r < nrhs; ++r)
-                if (h_live[r] && h_iters[r] >= p.maxiter) {
-                    h_live[r] = 0;
-                    done[r] = 1;
-                    failed_any = true;
-                }
-            CKR(push_ctl());
-            // p := r for the rhs that restart from scratch
-            CKE(S.kE(mask_a, mask_a));
-            // first iteration without the direction update, then graph replays
-            CKE(S.iteration(false));
-            int replays = 1;
-            double rr_last = -1;
-            int it_last = 0;
-            long launched = 1;
-            for (;;) {
-                // host-side bound: the device stops every rhs at maxiter, so this
-                // only trips if the device state stops advancing
-                if (launched > (long)p.maxiter + 8L * iters_per_graph) {
-                    failed_any = true;
-                    for (int r = 0; r < nrhs; ++r) done[r] = 1;
-                    break;
-                }
-                launched += (long)replays * iters_per_graph;
-                if (p.use_graph) {
-                    for (int k = 0; k < replays; ++k) CKE(hipGraphLaunch(w->gexec, s));
-                } else {
-                    for (int k = 0; k < replays * iters_per_graph; ++k) CKE(S.iteration(true));
-                }
-                CKR(pull());
-                bool alive = false;
-                double worst = 0;
-                int itmin = 1 << 30;
-                for (int r = 0; r < nrhs; ++r)
-                    if (h_live[r]) {
-                        alive = true;
-                        worst = std::max(worst, h_rr[r] / std::max(h_target[r], 1e-300));
-                        itmin = std::min(itmin, h_iters[r]);
+                } else if (sqrt(rh2) > 0.9 * q.rhat_prev) {
+                    if (++q.noprog >= 4) {
+                        q.failed = 1;
+                        q.phase = PH_FINAL;
+                        continue;
                     }
-                if (!alive) break;
-                // adapt the number of replays between checks to the convergence rate
-                if (rr_last > 0 && itmin > it_last && worst < rr_last) {
-                    double per_it = log(worst / rr_last) / (double)(itmin - it_last);
-                    double need = per_it < 0 ? log(worst) / -per_it : 1e9;
-                    replays = (int)std::min(64.0, std::max(1.0, 0.8 * need / iters_per_graph));
                 } else {
-                    replays = std::min(64, replays * 2);
+                    q.noprog = 0;
                 }
-                rr_last = worst;
-                it_last = itmin;
             }
-            // reliable updates: finish the last direction update p = r + beta p
-            // (Algorithm 1 computes p_{k+1} before testing convergence)
-            for (int r = 0; r < nrhs; ++r) h_mask[nrhs + r] = (mode_ru[r] && h_status[r] == 1 && !done[r]) ? 1 : 0;
-            DWF_HIP(hipMemcpyAsync(mask_b, h_mask + nrhs, nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-            CKE(S.kE(mask_b, nullptr));
-            // keep the current iterate, then yhat += y
-            CKE(half_copy(c, w->f(YH_E), w->f(YH_O), nrhs, nullptr, s));
-            for (int r = 0; r < nrhs; ++r) have_backup[r] = 1;
-            CKE(half_acc(c, w->f(YH_O), w->f(L_Y), nrhs, nullptr, s));
-            for (int r = 0; r < nrhs; ++r)
-                if (h_status[r] == 2 && !mode_ru[r]) {  // breakdown in defect correction: give up
-                    done[r] = 1;
-                    failed_any = true;
-                }
+            if (h_iters(r) >= q.p.maxiter) {  // iteration cap over all cycles
+                q.failed = 1;
+                q.phase = PH_FINAL;
+                continue;
+            }
+            q.rhat_prev = sqrt(rh2);
+            const double eps = q.mode_ru ? q.eps_ru : q.eps_dc;
+            const double stop = 0.5 * q.tol_schur * sqrt(q.bpp2);
+            const double tgt = std::max(eps * sqrt(rh2), stop);
+            h_target(r) = tgt * tgt;
+            h_live(r) = 1;
+            h_status(r) = 0;
+            h_maxiter(r) = q.p.maxiter;
+            // p := r on the first cycle, in defect correction and after a
+            // rejected cycle; reliable updates keep p
+            h_emode(r) = (q.cycles == 0 || !q.mode_ru || q.reverted) ? 1 : 2;
+            ++q.cycles;
+            q.phase = PH_INNER;
+            q.rr_last = -1;
+            q.stuck = 0;
+            if (getenv("DWF_VERBOSE"))
+                fprintf(stderr, "[dwf] slot %d cycle %d: |rhat|/|b''| = %.3e mode=%s iters=%d%s\n", r, q.cycles,
+                        rel, q.mode_ru ? "RU" : "DC", h_iters(r), q.reverted ? " (reverted)" : "");
         }
-        // ================= reconstruction and the true residual =================
-        // y_e = b'_e - M5 D^EO y_o ; x = S2 y  (into BP_E/BP_O)
-        CKE(S.xmy_m5hop64(0, YH_O, BP_E, YH_E, false));
-        CKE(S.local64(0, YH_E, TB_S2, BP_E));
-        CKE(S.local64(1, YH_O, TB_S2, BP_O));
-        // D x = X x + D_w (Y x) per parity; Y x -> YH_*, X x -> T64_E (even), BPP (odd)
-        // (BPP is rebuilt below if another round is needed)
-        CKE(S.local64(0, BP_E, TB_Y, YH_E));
-        CKE(S.local64(1, BP_O, TB_Y, T64_E));  // temporarily Yx_o in T64_E
-        std::vector<double> tr(nrhs, 0.0);
-        {
-            // even rows: b_e - X x_e - D^EO (Y x)_o ; X x_e -> YH_O is free? no: keep yhat_o.
-            // use BPP for X x_e, then odd rows with X x_o in BPP again.
-            CKE(S.local64(0, BP_E, TB_X, BPP));
-            CKE((launch_dwf<double, FD, LinkD18, true, MIX_NONE, ProLoad<FD>, EpiTrueRes<FD, FD>>(
-                S.g64(0), S.d(T64_E), S.lk64[0], nullptr, ProLoad<FD>{S.d(T64_E)},
-                EpiTrueRes<FD, FD>{S.d(B_E), S.d(BPP)}, S.kopt(nullptr, true), s)));
-            CKE(S.fin(nb64e, FIN_AUX));
-            CKR(pull());
-            for (int r = 0; r < nrhs; ++r) tr[r] = h_aux[r];
-            CKE(S.local64(1, BP_O, TB_X, BPP));
-            CKE((launch_dwf<double, FD, LinkD18, true, MIX_NONE, ProLoad<FD>, EpiTrueRes<FD, FD>>(
-                S.g64(1), S.d(YH_E), S.lk64[1], nullptr, ProLoad<FD>{S.d(YH_E)},
-                EpiTrueRes<FD, FD>{S.d(B_O), S.d(BPP)}, S.kopt(nullptr, true), s)));
-            CKE(S.fin(nb64o, FIN_AUX));
-            CKR(pull());
-            for (int r = 0; r < nrhs; ++r) tr[r] += h_aux[r];
-        }
-        bool again = false;
-        for (int r = 0; r < nrhs; ++r) {
-            true_res[r] = bnorm2[r] > 0 ? sqrt(tr[r] / bnorm2[r]) : sqrt(tr[r]);
-            if (true_res[r] > p.tol && done[r] && schur_res[r] <= tol_schur[r] && std::isfinite(true_res[r])) {
+        return push_ctl();
+    }
+
+    // ---- reconstruction y_e = b'_e - M5 D^EO y_o, x = S2 y, and |b - D x| / |b|
+    int final_check() {
+        int* m = dmask[M_FINAL];
+        upload_mask(M_FINAL, [&](int r) { return sl[r].phase == PH_FINAL; });
+        CKE(xmy_m5hop64(0, YH_O, BP_E, YH_E, false, m));
+        CKE(local64(0, YH_E, TB_S2, BP_E, m));
+        CKE(local64(1, YH_O, TB_S2, BP_O, m));
+        // D x = X x + D_w (Y x) per parity: Y x -> YH_E (even), T64_E (odd);
+        // X x -> BPP one parity at a time
+        CKE(local64(0, BP_E, TB_Y, YH_E, m));
+        CKE(local64(1, BP_O, TB_Y, T64_E, m));
+        CKE(local64(0, BP_E, TB_X, BPP, m));
+        CKE(true_res(0, T64_E, B_E, BPP, m));
+        CKE(fin(g64(0).nblocks, FIN_AUX, m));
+        CKR(pull());
+        std::vector<double> tr(K, 0.0);
+        for (int r = 0; r < K; ++r) tr[r] = h_aux(r);
+        CKE(local64(1, BP_O, TB_X, BPP, m));
+        CKE(true_res(1, YH_E, B_O, BPP, m));
+        CKE(fin(g64(1).nblocks, FIN_AUX, m));
+        CKR(pull());
+        const auto now = std::chrono::steady_clock::now();
+        for (int r = 0; r < K; ++r) {
+            if (!hmask[M_FINAL][r]) continue;
+            SlotCtl& q = sl[r];
+            tr[r] += h_aux(r);
+            q.true_res = q.bnorm2 > 0 ? sqrt(tr[r] / q.bnorm2) : sqrt(tr[r]);
+            if (q.true_res > q.p.tol && !q.failed && q.schur_res <= q.tol_schur && std::isfinite(q.true_res) &&
+                q.round < 5) {
                 // tighten the Schur target and continue from the current iterate
-                tol_schur[r] *= std::max(0.01, 0.5 * p.tol / true_res[r]);
-                done[r] = 0;
-                again = true;
+                q.tol_schur *= std::max(0.01, 0.5 * q.p.tol / q.true_res);
+                q.round++;
+                q.have_backup = 0;  // YH_E was overwritten
+                q.phase = PH_OUTER;
+            } else {
+                q.phase = PH_DONE;
+                q.seconds = std::chrono::duration<double>(now - q.t0).count();
             }
         }
-        if (!again || round == 5) break;
         // restore the pieces the reconstruction overwrote: b' and b''
-        CKE(S.local64(0, B_E, TB_S1, BP_E));
-        CKE(S.local64(1, B_O, TB_S1, BP_O));
-        CKE(S.xmy_m5hop64(1, BP_E, BP_O, BPP, false));
-    }
-    // the last reconstruction left x in BP_E/BP_O
-    CKE(half_to_host(c, w->f(BP_E), w->f(BP_O), nrhs, x_dev, s));
-    DWF_HIP(hipEventRecord(ev1, s));
-    CKR(pull());
-    DWF_HIP(hipEventSynchronize(ev1));
-    float ms = 0;
-    DWF_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-    int status = DWF_OK;
-    for (int r = 0; r < nrhs; ++r)
-        if (!(true_res[r] <= p.tol)) status = DWF_ENOCONV;
-    if (failed_any) status = DWF_ENOCONV;
-    if (stats) {
-        const double fi = flops_per_iter(c);
-        const double bi = bytes_per_iter(c, prec, link_fmt);
-        const double V = (double)c->V5h;
-        const double fo = V * (2640.0 + 96.0 * c->Ns + 72.0);
-        const double fsetup = V * (144.0 * c->Ns + 1392.0);
-        const double ffinal = V * (336.0 * c->Ns + 4080.0);
-        long tot_it = 0;
-        for (int r = 0; r < nrhs; ++r) tot_it += h_iters[r];
-        for (int r = 0; r < nrhs; ++r) {
-            dwf_solve_stats& o = stats[r];
-            memset(&o, 0, sizeof(o));
-            o.status = (true_res[r] <= p.tol) ? DWF_OK : DWF_ENOCONV;
-            o.iters = h_iters[r];
-            o.restarts = restarts;
-            o.reliable_updates = ru_restarts[r];
-            o.fallback = fellback[r];
-            o.true_residual = true_res[r];
-            o.schur_residual = schur_res[r];
-            o.seconds = ms * 1e-3;
-            const double flops = fi * tot_it + (fo * restarts + fsetup + ffinal) * nrhs;
-            o.gflops = o.seconds > 0 ? flops / o.seconds * 1e-9 : 0;
-            o.hbm_gbytes = (bi * tot_it + 12.0 * V * 192.0 * (restarts + 4) * nrhs) * 1e-9;
+        int na = upload_mask(M_AGAIN, [&](int r) { return hmask[M_FINAL][r] && sl[r].phase == PH_OUTER; });
+        if (na) {
+            CKE(local64(0, B_E, TB_S1, BP_E, dmask[M_AGAIN]));
+            CKE(local64(1, B_O, TB_S1, BP_O, dmask[M_AGAIN]));
+            CKE(xmy_m5hop64(1, BP_E, BP_O, BPP, false, dmask[M_AGAIN]));
         }
+        return DWF_OK;
     }
-    if (status != DWF_OK) fail(DWF_ENOCONV, "solve did not reach the requested tolerance");
-    return status;
+
+    // ---- a run of inner iterations for every live slot, then the slots whose
+    // inner cycle ended go on to the outer step
+    int inner() {
+        int check = 0;
+        for (int r = 0; r < K; ++r)
+            if (sl[r].phase == PH_INNER && sl[r].p.check_every > 0)
+                check = check ? std::min(check, sl[r].p.check_every) : sl[r].p.check_every;
+        int n = check ? std::max(1, (check + kItersPerGraph - 1) / kItersPerGraph) : plan_replays();
+        if (use_graph) {
+            CKR(ensure_graph());
+            for (int k = 0; k < n; ++k) CKE(hipGraphLaunch(w.gexec, s));
+        } else {
+            for (int k = 0; k < n * kItersPerGraph; ++k) CKE(iteration());
+        }
+        std::vector<int> before(K);
+        for (int r = 0; r < K; ++r) before[r] = h_iters(r);
+        CKR(pull());
+        bool ended = false;
+        for (int r = 0; r < K; ++r) {
+            if (sl[r].phase != PH_INNER) continue;
+            SlotCtl& q = sl[r];
+            if (!h_live(r)) {
+                ended = true;
+                continue;
+            }
+            // the device stops every slot at maxiter; this only trips if the
+            // device state stops advancing
+            if (h_iters(r) == before[r] && ++q.stuck >= 3) return fail(DWF_EDEVICE, "inner solve does not advance");
+            // convergence rate per iteration, kept across cycles
+            const double rr = h_rr(r);
+            if (q.rr_last > 0 && h_iters(r) > q.it_last && rr < q.rr_last && rr > 0)
+                q.rate = log(rr / q.rr_last) / (double)(h_iters(r) - q.it_last);
+            q.rr_last = rr;
+            q.it_last = h_iters(r);
+        }
+        if (ended) CKR(post_cycle());
+        return DWF_OK;
+    }
+
+    // graph replays until the first live slot is expected to end its cycle
+    int plan_replays() {
+        double need = 1e30;
+        for (int r = 0; r < K; ++r) {
+            if (sl[r].phase != PH_INNER) continue;
+            SlotCtl& q = sl[r];
+            const double rr = q.rr_last > 0 ? q.rr_last : h_aux(r);
+            double nr;
+            if (q.rate < 0 && rr > 0 && h_target(r) > 0) {
+                nr = std::max(1.0, 0.8 * log(h_target(r) / rr) / q.rate);
+            } else {  // no rate yet: probe with a doubling number of iterations
+                nr = (double)q.probe * kItersPerGraph;
+                q.probe = std::min(64, q.probe * 2);
+            }
+            need = std::min(need, nr);
+        }
+        replays = (int)std::min((double)replay_cap, std::max(1.0, need / kItersPerGraph));
+        return replays;
+    }
+
+    // the slots whose inner cycle ended: finish p for reliable updates,
+    // keep yhat (backup), yhat += y
+    int post_cycle() {
+        int nfin = upload_mask(M_RUFIN, [&](int r) {
+            return sl[r].phase == PH_INNER && !h_live(r) && sl[r].mode_ru && h_status(r) == 1;
+        });
+        // reliable updates: the last direction update p = r + beta p
+        // (Algorithm 1 computes p_{k+1} before testing convergence)
+        if (nfin) CKE(kE(dmask[M_RUFIN], nullptr));
+        upload_mask(M_POST, [&](int r) { return sl[r].phase == PH_INNER && !h_live(r); });
+        CKE(half_copy(c, w.f(YH_E), w.f(YH_O), K, dmask[M_POST], s));
+        CKE(half_acc(c, w.f(YH_O), w.f(L_Y), K, dmask[M_POST], s));
+        for (int r = 0; r < K; ++r) {
+            if (!hmask[M_POST][r]) continue;
+            SlotCtl& q = sl[r];
+            q.have_backup = 1;
+            if (h_status(r) == 2 && !q.mode_ru) {  // breakdown in defect correction: give up
+                q.failed = 1;
+                q.phase = PH_FINAL;
+            } else {
+                q.phase = PH_OUTER;
+            }
+        }
+        return DWF_OK;
+    }
 #undef CKE
 #undef CKR
-}
+};
 
 template <class Real, class F, class FY, class LF>
-int time_kernels(dwf_ctx* c, const dwf_solve_params& p, int nrhs, int launches, double* ms, double* bytes,
-                 int link_fmt, LF lke, LF lko) {
-    int rc;
-    const TableSet* ts = c->table_set(c->mq, &rc);
-    if (!ts) return rc;
-    std::string key = "solve:" + std::to_string(p.inner_prec) + ":" + std::to_string(link_fmt) + ":" +
-                      std::to_string(nrhs);
-    auto it = c->ws.find(key);
-    auto ip = c->ws.find(key + ":aux");
-    if (it == c->ws.end() || !it->second || ip == c->ws.end() || !ip->second)
-        return fail(DWF_EINVAL, "no solve workspace for these parameters; run a solve first");
-    Workspace* w = it->second.get();
-    DevBuf* partials_buf = &ip->second->state;
-    hipStream_t s = c->stream;
-    Solver<Real, F, FY, LF> S{c, ts, w, {lke, lko},
-                              {LinkD18{c->links[0][LINK_D18].as<double>()}, LinkD18{c->links[1][LINK_D18].as<double>()}},
-                              nrhs, s, partials_buf, nullptr, nullptr, p};
-    // all kernels forced on (live = NULL); A, C are idempotent, B/D/E update
-    // their outputs from finite inputs
+int Engine<Real, F, FY, LF>::time_kernels(int launches, double* ms, double* bytes) {
+    // all kernels forced on (live = NULL); A and C are idempotent, B, D and E
+    // update their outputs from finite inputs
     auto runk = [&](int k) -> hipError_t {
-        const int* nolive = nullptr;
         switch (k) {
-            case 0: return S.kE(nolive, nullptr);
-            case 1:
-                return launch_dwf<Real, F, LF, true, MIX_AS, ProLoad<F>, EpiStore<F>>(
-                    S.glo(0), S.lo(L_T1), S.lk[0], S.slo(ST_M5T), ProLoad<F>{S.lo(L_T1)}, EpiStore<F>{S.lo(L_T23)},
-                    S.kopt(nolive, false), s);
-            case 2:
-                return launch_dwf<Real, F, LF, true, MIX_NONE, ProLoad<F>, EpiCgB<F, F>>(
-                    S.glo(1), S.lo(L_T23), S.lk[1], nullptr, ProLoad<F>{S.lo(L_T23)}, EpiCgB<F, F>{S.lo(L_P), S.lo(L_U)},
-                    S.kopt(nolive, true), s);
-            case 3:
-                return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiStore<F>>(
-                    S.glo(0), S.lo(L_U), S.lk[0], S.slo(ST_M5), ProLoad<F>{S.lo(L_U)}, EpiStore<F>{S.lo(L_T23)},
-                    S.kopt(nolive, false), s);
-            default:
-                return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiCgD<F, F, FY>>(
-                    S.glo(1), S.lo(L_T23), S.lk[1], S.slo(ST_M5), ProLoad<F>{S.lo(L_T23)},
-                    EpiCgD<F, F, FY>{S.lo(L_U), S.lo(L_R), S.ylo(), w->st.alpha}, S.kopt(nolive, true), s);
+            case 0: return kE(nullptr, nullptr);
+            case 1: return kA(nullptr);
+            case 2: return kB(nullptr);
+            case 3: return kC(nullptr);
+            default: return kD(nullptr);
         }
     };
     // one event pair around every launch: the average is the kernels' own
     // device time, without the dispatch gap between back-to-back launches
     std::vector<hipEvent_t> ev(2 * (size_t)launches, nullptr);
     for (auto& e : ev) DWF_HIP(hipEventCreate(&e));
-    const double sb = spinor_bytes(p.inner_prec) * (double)c->V5h * nrhs;
-    const double yb = (p.inner_prec == DWF_PREC_FP64 ? 192.0 : 96.0) * (double)c->V5h * nrhs;
+    const double sb = spinor_bytes(prec) * (double)c->V5h * K;
+    const double yb = (prec == DWF_PREC_FP64 ? 192.0 : 96.0) * (double)c->V5h * K;
     const double lb = (double)c->V4h * 8.0 * link_bytes(link_fmt);
     const double model[5] = {4 * sb, 2 * sb + lb, 3 * sb + lb, 2 * sb + lb, 4 * sb + 2 * yb + lb};
     int result = DWF_OK;
@@ -646,48 +706,135 @@ int time_kernels(dwf_ctx* c, const dwf_solve_params& p, int nrhs, int launches, 
     return result;
 }
 
+template <class Real, class F, class FY, class LF>
+int build(dwf_ctx* c, int prec, int fmt, int K, hipStream_t s, LF e, LF o, std::unique_ptr<EngineBase>* out) {
+    std::unique_ptr<Engine<Real, F, FY, LF>> eng(new Engine<Real, F, FY, LF>(c, prec, fmt, K, s, e, o));
+    int rc = eng->init();
+    if (rc) return rc;
+    *out = std::move(eng);
+    return DWF_OK;
+}
+
+std::string engine_key(const dwf_solve_params& p, int nrhs) {
+    return "solve:" + std::to_string(p.inner_prec) + ":" + std::to_string(link_format(p)) + ":" +
+           std::to_string(nrhs);
+}
+
 }  // namespace
 
-int time_inner_kernels(dwf_ctx* c, const dwf_solve_params& p, int nrhs, int launches, double* ms, double* bytes) {
-    const LinkD18 d0{c->links[0][LINK_D18].as<double>()}, d1{c->links[1][LINK_D18].as<double>()};
+int make_engine(dwf_ctx* c, const dwf_solve_params& p, int K, hipStream_t s, std::unique_ptr<EngineBase>* out) {
     switch (p.inner_prec) {
         case DWF_PREC_FP64:
-            return time_kernels<double, FD, FD, LinkD18>(c, p, nrhs, launches, ms, bytes, LINK_D18, d0, d1);
+            return build<double, FD, FD, LinkD18>(c, DWF_PREC_FP64, LINK_D18, K, s,
+                                                  LinkD18{c->links[0][LINK_D18].as<double>()},
+                                                  LinkD18{c->links[1][LINK_D18].as<double>()}, out);
         case DWF_PREC_FP32:
             if (p.link_compress == 1)
-                return time_kernels<float, FS, FS, LinkS12>(c, p, nrhs, launches, ms, bytes, LINK_S12,
-                                                            LinkS12{c->links[0][LINK_S12].as<float>()},
-                                                            LinkS12{c->links[1][LINK_S12].as<float>()});
-            return time_kernels<float, FS, FS, LinkS18>(c, p, nrhs, launches, ms, bytes, LINK_S18,
-                                                        LinkS18{c->links[0][LINK_S18].as<float>()},
-                                                        LinkS18{c->links[1][LINK_S18].as<float>()});
+                return build<float, FS, FS, LinkS12>(c, DWF_PREC_FP32, LINK_S12, K, s,
+                                                     LinkS12{c->links[0][LINK_S12].as<float>()},
+                                                     LinkS12{c->links[1][LINK_S12].as<float>()}, out);
+            return build<float, FS, FS, LinkS18>(c, DWF_PREC_FP32, LINK_S18, K, s,
+                                                 LinkS18{c->links[0][LINK_S18].as<float>()},
+                                                 LinkS18{c->links[1][LINK_S18].as<float>()}, out);
         default:
-            return time_kernels<float, FH, FS, LinkH12>(c, p, nrhs, launches, ms, bytes, LINK_H12,
-                                                        LinkH12{c->links[0][LINK_H12].as<_Float16>()},
-                                                        LinkH12{c->links[1][LINK_H12].as<_Float16>()});
+            return build<float, FH, FS, LinkH12>(c, DWF_PREC_FP16, LINK_H12, K, s,
+                                                 LinkH12{c->links[0][LINK_H12].as<_Float16>()},
+                                                 LinkH12{c->links[1][LINK_H12].as<_Float16>()}, out);
     }
 }
 
+size_t engine_bytes(const dwf_ctx* c, int prec, int K) {
+    const long lo = field_elems(c->V5h, prec);
+    const long y = field_elems(c->V5h, prec == DWF_PREC_FP64 ? DWF_PREC_FP64 : DWF_PREC_FP32);
+    const long f64 = field_elems(c->V5h, DWF_PREC_FP64);
+    size_t per = ((size_t)NF64 * f64 + 5 * (size_t)lo + (size_t)y) * 16;
+    if (prec == DWF_PREC_FP16) per += 5 * (size_t)(((c->V5h + 1023) / 1024) * 1024) * sizeof(float);
+    const size_t nb = (size_t)std::max(c->geom(0, true).nblocks, c->geom(0, false).nblocks);
+    per += tables_size(c->Ns) * 12 + nb * sizeof(double) + 96;
+    return per * (size_t)K;
+}
+
 int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params& p,
-          dwf_solve_stats* stats, hipStream_t s, const double* mq_per_rhs) {
-    (void)mq_per_rhs;
-    const LinkD18 d0{c->links[0][LINK_D18].as<double>()}, d1{c->links[1][LINK_D18].as<double>()};
-    switch (p.inner_prec) {
-        case DWF_PREC_FP64:
-            return run_solve<double, FD, FD, LinkD18>(c, b_dev, x_dev, nrhs, p, stats, s, LINK_D18, d0, d1);
-        case DWF_PREC_FP32:
-            if (p.link_compress == 1)
-                return run_solve<float, FS, FS, LinkS12>(c, b_dev, x_dev, nrhs, p, stats, s, LINK_S12,
-                                                         LinkS12{c->links[0][LINK_S12].as<float>()},
-                                                         LinkS12{c->links[1][LINK_S12].as<float>()});
-            return run_solve<float, FS, FS, LinkS18>(c, b_dev, x_dev, nrhs, p, stats, s, LINK_S18,
-                                                     LinkS18{c->links[0][LINK_S18].as<float>()},
-                                                     LinkS18{c->links[1][LINK_S18].as<float>()});
-        default:
-            return run_solve<float, FH, FS, LinkH12>(c, b_dev, x_dev, nrhs, p, stats, s, LINK_H12,
-                                                     LinkH12{c->links[0][LINK_H12].as<_Float16>()},
-                                                     LinkH12{c->links[1][LINK_H12].as<_Float16>()});
+          dwf_solve_stats* stats, hipStream_t s) {
+    const std::string key = engine_key(p, nrhs);
+    auto& slot = c->engines[key];
+    if (!slot) {
+        int rc = make_engine(c, p, nrhs, s, &slot);
+        if (rc) {
+            slot.reset();
+            return rc;
+        }
     }
+    EngineBase* eng = slot.get();
+    eng->set_stream(s);
+    eng->set_use_graph(p.use_graph != 0);
+    const long n5 = c->V4 * c->Ns * 24;
+
+    hipEvent_t ev0, ev1;
+    DWF_HIP(hipEventCreate(&ev0));
+    DWF_HIP(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } evg{ev0, ev1};
+    DWF_HIP(hipEventRecord(ev0, s));
+
+    // after an error the engine's slots are in an unknown state: drop it
+    auto abandon = [&](int rc) {
+        std::string msg = dwf_last_error();
+        (void)hipStreamSynchronize(s);
+        c->engines.erase(key);
+        return fail(rc, msg);
+    };
+    int rc;
+    for (int r = 0; r < nrhs; ++r)
+        if ((rc = eng->admit(r, b_dev + r * n5, p.use_guess ? x_dev + r * n5 : nullptr, c->mq, p)))
+            return abandon(rc);
+    // every tick either advances a slot's phase or runs inner iterations,
+    // which end at the device-side iteration cap
+    while (eng->pending() > 0)
+        if ((rc = eng->tick())) return abandon(rc);
+    std::vector<SlotResult> res(nrhs);
+    for (int r = 0; r < nrhs; ++r)
+        if ((rc = eng->retire(r, x_dev + r * n5, &res[r]))) return abandon(rc);
+    DWF_HIP(hipEventRecord(ev1, s));
+    DWF_HIP(hipEventSynchronize(ev1));
+    float ms = 0;
+    DWF_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    int status = DWF_OK;
+    double flops = 0, bytes = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        if (res[r].status != DWF_OK) status = DWF_ENOCONV;
+        flops += res[r].flops;
+        bytes += res[r].bytes;
+    }
+    if (stats) {
+        for (int r = 0; r < nrhs; ++r) {
+            dwf_solve_stats& o = stats[r];
+            memset(&o, 0, sizeof(o));
+            o.status = res[r].status;
+            o.iters = res[r].iters;
+            o.restarts = res[r].restarts;
+            o.reliable_updates = res[r].reliable_updates;
+            o.fallback = res[r].fallback;
+            o.true_residual = res[r].true_residual;
+            o.schur_residual = res[r].schur_residual;
+            // the batch shares the device: time, rate and bytes are the batch's
+            o.seconds = ms * 1e-3;
+            o.gflops = o.seconds > 0 ? flops / o.seconds * 1e-9 : 0;
+            o.hbm_gbytes = bytes * 1e-9;
+        }
+    }
+    if (status != DWF_OK) fail(DWF_ENOCONV, "solve did not reach the requested tolerance");
+    return status;
+}
+
+int time_inner_kernels(dwf_ctx* c, const dwf_solve_params& p, int nrhs, int launches, double* ms, double* bytes) {
+    auto it = c->engines.find(engine_key(p, nrhs));
+    if (it == c->engines.end() || !it->second)
+        return fail(DWF_EINVAL, "no solve workspace for these parameters; run a solve first");
+    it->second->set_stream(c->stream);
+    return it->second->time_kernels(launches, ms, bytes);
 }
 
 }  // namespace dwf

@@ -102,3 +102,19 @@ def test_missing_library_fails_loudly(tmp_path):
     ) % (ROOT, str(tmp_path / "missing.so"))
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True).stdout
     assert "RAISED" in out
+
+
+def test_server_entry_points_without_a_device():
+    """Ticket lookup, statistics and argument checks of the request server need
+    no GPU: an unknown ticket is DWF_ENOTFOUND, NULL arguments DWF_EINVAL."""
+    import paper_1101_0423_amd as dwf
+    L = dwf.lib()
+    st = dwf.SolveStats()
+    assert L.dwf_poll(ctypes.c_uint64(123456789), None, ctypes.byref(st), 0) == dwf.DWF_ENOTFOUND
+    assert "ticket" in L.dwf_last_error().decode()
+    t = ctypes.c_uint64()
+    assert L.dwf_submit(None, None, None, ctypes.byref(t)) == dwf.DWF_EINVAL
+    assert L.dwf_submit_mass(None, None, 0.1, None, ctypes.byref(t)) == dwf.DWF_EINVAL
+    assert L.dwf_server_stats_get(None, 0) == dwf.DWF_EINVAL
+    s = dwf.server_stats(reset=True)
+    assert s["completed"] == 0 and s["waits_for_memory"] == 0 and s["p99_latency"] == 0.0
