@@ -110,6 +110,200 @@ def summarize_rocpd(path):
         print(f"{kernel_label(name):40s} {n:8d} {s / 1e6:10.2f} {a / 1e3:9.2f} {100 * s / tot:5.1f}%")
 
 
+def _ctx(dwf, U, w, **kw):
+    return dwf.Context(U, w["dims"], w["ns"], w["m0"], w["mq"], w["sigma"], w["omega"], device=0, **kw)
+
+
+def batch_bench(args):
+    """24^3 x 48, Ns = 16 Shamir, 12 point sources: one 12-right-hand-side
+    solve against 12 single-right-hand-side solves of the same sources."""
+    import numpy as np
+    import torch
+
+    import dwf_inputs as inp
+    import paper_1101_0423_amd as dwf
+
+    wname = "shamir_24x24x24x48_ns16_12pt"
+    w = inp.workload(wname)
+    dims, ns = w["dims"], w["ns"]
+    nrhs = args.nrhs
+    print(f"[bench] generating {wname}", file=sys.stderr, flush=True)
+    U = inp.gauge_field(dims, w["eps"], seed=w["seed_gauge"])
+    torch.cuda.set_device(0)
+    ctx = _ctx(dwf, U, w)
+    B = torch.empty((nrhs,) + ctx.spinor_shape(), dtype=torch.float64, device="cuda")
+    for k in range(nrhs):
+        B[k].copy_(torch.from_numpy(inp.point_source(dims, ns, k, seed=w["seed_rhs"])))
+    X = torch.zeros_like(B)
+    X1 = torch.zeros_like(B[0])
+    params = dwf.default_params(inner_prec=1, tol=1e-10)
+    # build both engines (and their graphs) outside the timed region
+    warm = dwf.default_params(inner_prec=1, tol=1e-10, maxiter=8)
+    ctx.solve_dev(B, X, nrhs=nrhs, params=warm)
+    ctx.solve_dev(B[0], X1, nrhs=1, params=warm)
+    X.zero_()
+    X1.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_b, rc_b = ctx.solve_dev(B, X, nrhs=nrhs, params=params)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"[bench] batched {nrhs}: rc={rc_b} {t_batch:.2f}s iters={[s['iters'] for s in st_b]}",
+          file=sys.stderr, flush=True)
+    ms_b, by_b = ctx.time_kernels(params=params, nrhs=nrhs, launches=5)
+    t_seq, st_s, diff = 0.0, [], 0.0
+    for k in range(nrhs):
+        X1.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rc = ctx.solve_dev(B[k], X1, nrhs=1, params=params)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        st_s.append((st[0], rc))
+        diff = max(diff, float(torch.linalg.vector_norm(X[k] - X1) / torch.linalg.vector_norm(X1)))
+        print(f"[bench] single {k}: rc={rc} {st[0]['seconds']:.2f}s iters={st[0]['iters']}", file=sys.stderr,
+              flush=True)
+    ms_1, by_1 = ctx.time_kernels(params=params, nrhs=1, launches=5)
+    flops = sum(s["gflops"] for s in st_b[:1]) * st_b[0]["seconds"] * 1e9
+    names = {"E": "cg_dir_m5t", "A": "hop_eo_m5t", "B": "hop_oe_g5_sub", "C": "hop_eo_m5", "D": "hop_oe_m5_cgupd"}
+    kern = {names[k]: dict(ms_batch=round(ms_b[k], 4), ms_single=round(ms_1[k], 4),
+                           gbs_batch=round(by_b[k] / (ms_b[k] * 1e-3) * 1e-9, 1),
+                           gbs_single=round(by_1[k] / (ms_1[k] * 1e-3) * 1e-9, 1)) for k in ms_b}
+    line = dict(metric="batched solves/s (24^3x48, Ns=16, 12 point sources)", value=round(nrhs / t_batch, 4),
+                unit="solves/s", n_gpus=1, steps=1, warmup=1, ms_per_step=round(t_batch * 1e3, 1),
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32 inner / f64 outer",
+                data="synthetic",
+                config=dict(workload=f"{wname}: 24^3x48 lattice, Ns=16 Shamir, m0=1.8, mq=0.005, SU(3) links "
+                                     f"eps=0.5, {nrhs} point sources at one seeded 5D site, tol 1e-10",
+                            nrhs=nrhs),
+                sequential_solves_per_s=round(nrhs / t_seq, 4), speedup=round(t_seq / t_batch, 3),
+                batch_gflops=round(flops / t_batch * 1e-9, 1),
+                converged=all(s["status"] == 0 for s in st_b) and all(rc == 0 for _, rc in st_s),
+                max_true_residual=max(s["true_residual"] for s in st_b),
+                batch_vs_single_max_rel_diff=diff, iters=[s["iters"] for s in st_b],
+                rhs_per_workgroup=st_b[0]["rhs_per_block"], kernels=kern)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def serve_bench(args):
+    """Poisson stream of independent solves on four resident fields (every
+    (field, Ns) pair is one context), served by dwf_submit/dwf_poll, against a
+    FIFO server of plain single-right-hand-side solves on the same stream."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import dwf_inputs as inp
+    import paper_1101_0423_amd as dwf
+
+    torch.cuda.set_device(0)
+    reqs = inp.serve_stream(args.requests)
+    used = sorted({(r["field"], r["ns"]) for r in reqs})
+    ctxs, rhs, gauges = {}, {}, {}
+    for f, ns in used:
+        o = inp.serve_operator(f, ns)
+        if f not in gauges:
+            gauges[f] = inp.gauge_field(o["dims"], o["eps"], seed=o["seed_gauge"])
+        ctxs[(f, ns)] = dwf.Context(gauges[f], o["dims"], ns, o["m0"], inp.SERVE_MQ[0], o["sigma"], o["omega"],
+                                    device=0)
+        for k in range(inp.SERVE_RHS_PER_OPERATOR):
+            rhs[(f, ns, k)] = inp.gaussian_spinor(o["dims"], ns, seed=inp.serve_rhs_seed(f, ns, k))
+    print(f"[bench] {len(ctxs)} operators resident", file=sys.stderr, flush=True)
+    params = dwf.default_params(inner_prec=1, tol=1e-10)
+    # plain single-right-hand-side service time of every request type (a
+    # context per mass, so that dwf_solve runs that mass)
+    svc = {}
+    for r in reqs:
+        key = (r["field"], r["ns"], r["mq"])
+        if key in svc:
+            continue
+        o = inp.serve_operator(r["field"], r["ns"])
+        c = dwf.Context(gauges[r["field"]], o["dims"], r["ns"], o["m0"], r["mq"], o["sigma"], o["omega"], device=0)
+        b = rhs[(r["field"], r["ns"], 0)]
+        c.solve(b, params=dwf.default_params(inner_prec=1, tol=1e-10, maxiter=8))  # engine and graph
+        t0 = time.perf_counter()
+        x, st, rc = c.solve(b, params=params)
+        svc[key] = time.perf_counter() - t0
+        c.close()
+        print(f"[bench] service {key}: {svc[key]:.3f}s iters={st[0]['iters']}", file=sys.stderr, flush=True)
+    mean_svc = float(np.mean([svc[(r["field"], r["ns"], r["mq"])] for r in reqs]))
+    if args.load > 0:
+        rate = args.load / mean_svc
+        arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
+        arrivals -= arrivals[0]
+    else:  # saturated: every request is there at the start
+        arrivals = np.zeros(len(reqs))
+    # FIFO single-right-hand-side server: each request starts when it has
+    # arrived and the previous one is done
+    done, fifo_lat = 0.0, []
+    for r, a in zip(reqs, arrivals):
+        done = max(done, a) + svc[(r["field"], r["ns"], r["mq"])]
+        fifo_lat.append(done - a)
+    fifo_span = done
+    # warm the server: one request per operator builds its lane
+    warm = [ctxs[k].submit(rhs[k + (0,)], mq=inp.SERVE_MQ[-1], params=params) for k in ctxs]
+    for t, k in zip(warm, ctxs):
+        while dwf.poll(t, ctxs[k].spinor_shape(), timeout_us=100000)[0] == dwf.DWF_PENDING:
+            pass
+    dwf.server_stats(reset=True)
+    tickets = [None] * len(reqs)
+    t_start = time.perf_counter()
+
+    def submitter():
+        for i, (r, a) in enumerate(zip(reqs, arrivals)):
+            delay = t_start + a - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            k = (r["field"], r["ns"])
+            tickets[i] = ctxs[k].submit(rhs[k + (r["rhs"],)], mq=r["mq"], params=params)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    pending = set(range(len(reqs)))
+    results = [None] * len(reqs)
+    while pending:
+        for i in list(pending):
+            if tickets[i] is None:
+                continue
+            r = reqs[i]
+            rc, x, st = dwf.poll(tickets[i], ctxs[(r["field"], r["ns"])].spinor_shape(), timeout_us=0)
+            if rc != dwf.DWF_PENDING:
+                results[i] = (rc, st["true_residual"], time.perf_counter() - t_start - arrivals[i])
+                pending.discard(i)
+        time.sleep(0.002)
+    span = time.perf_counter() - t_start
+    th.join()
+    s = dwf.server_stats()
+    ok = all(rc == dwf.DWF_OK for rc, _, _ in results)
+    lat = np.array([l for _, _, l in results])
+    line = dict(metric="served solves/s, p99 latency (Poisson stream, 4 resident fields)",
+                value=round(len(reqs) / span, 4), unit="solves/s", n_gpus=1, steps=len(reqs), warmup=len(warm),
+                ms_per_step=round(span / len(reqs) * 1e3, 2), higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="f32 inner / f64 outer", data="synthetic",
+                config=dict(workload=f"{len(reqs)} requests, "
+                                     + (f"Poisson arrivals at {args.load} x the plain single-RHS service rate"
+                                        if args.load > 0 else "all submitted at once (saturated)")
+                                     + f"; fields 8^3x16, 12^3x24, 2x 16^3x32 (eps 0.5); "
+                                     f"Ns in {{8,16,32}}, mq in {{0.01,0.03,0.1}}, sigma=omega~U[0.5,1.5], "
+                                     f"Gaussian RHS, tol 1e-10", requests=len(reqs), load=args.load),
+                p50_latency_s=round(s["p50_latency"], 4), p99_latency_s=round(s["p99_latency"], 4),
+                p50_latency_from_arrival_s=round(float(np.percentile(lat, 50)), 4),
+                p99_latency_from_arrival_s=round(float(np.percentile(lat, 99)), 4),
+                peak_batch=s["peak_batch"], waits_for_memory=s["waits_for_memory"], busy_s=round(s["busy_seconds"], 3),
+                fifo=dict(solves_per_s=round(len(reqs) / fifo_span, 4),
+                          p50_latency_s=round(float(np.percentile(fifo_lat, 50)), 4),
+                          p99_latency_s=round(float(np.percentile(fifo_lat, 99)), 4),
+                          kind="plain single-RHS solves in arrival order; service times measured per request "
+                               "type on this GPU"),
+                mean_plain_service_s=round(mean_svc, 4), converged=ok,
+                max_true_residual=max(r for _, r, _ in results))
+    for c in ctxs.values():
+        c.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,9 +312,14 @@ def main():
     ap.add_argument("--prec", choices=sorted(WORKLOADS), default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=20)
-    ap.add_argument("--mode", choices=["solve", "kernels"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "kernels", "batch", "serve"], default="solve",
                     help="kernels: one short solve without graphs, then each inner kernel timed "
-                         "(the driver for counter runs)")
+                         "(the driver for counter runs); batch: 12 point sources on 24^3x48, Ns=16, "
+                         "batched vs sequential; serve: Poisson request stream, served vs FIFO")
+    ap.add_argument("--nrhs", type=int, default=12, help="batch mode: right-hand sides")
+    ap.add_argument("--requests", type=int, default=200, help="serve mode: requests in the stream")
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="serve mode: arrival rate / plain service rate (0: all requests at once)")
     ap.add_argument("--summarize-rocpd", metavar="DB", help="print per-kernel statistics of a rocprofv3 "
                     "results database (kernel trace or --pmc) and exit")
     args = ap.parse_args()
@@ -131,6 +330,11 @@ def main():
         print("bench.py: this build measures one GPU only; there is no multi-GPU path "
               "(a single solve would shard by 4D domain decomposition, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "batch":
+        return batch_bench(args)
+    if args.mode == "serve":
+        return serve_bench(args)
 
     import numpy as np
     import torch

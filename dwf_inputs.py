@@ -121,6 +121,17 @@ def point_sources(dims, ns, seed=SEED_RHS):
     return out, (x, y, z, t, s)
 
 
+def point_source(dims, ns, k, seed=SEED_RHS):
+    """Source k (spin-colour component k) of point_sources, built alone."""
+    lx, ly, lz, lt = dims
+    rng = _rng(seed)
+    x, y, z, t = (int(rng.integers(0, n)) for n in (lx, ly, lz, lt))
+    s = int(rng.integers(0, ns))
+    out = np.zeros((lt, lz, ly, lx, ns, 24), dtype=np.float64)
+    out[t, z, y, x, s, 2 * k] = 1.0
+    return out
+
+
 def uniform_weights(ns, lo, hi, seed):
     """Per-slice weights drawn uniformly from [lo, hi]."""
     return _rng(seed).uniform(lo, hi, size=ns)
@@ -152,3 +163,42 @@ def workload(name):
                     sigma=np.zeros(ns), omega=np.ones(ns), eps=0.5,
                     seed_gauge=SEED_GAUGE + 3, seed_rhs=SEED_RHS + 3)
     raise KeyError(name)
+
+
+# ---------------------------------------------------------------------------
+# The served workload: a Poisson stream of independent solves on four
+# resident gauge fields.
+# ---------------------------------------------------------------------------
+
+SERVE_FIELDS = (((8, 8, 8, 16), SEED_GAUGE + 41), ((12, 12, 12, 24), SEED_GAUGE + 42),
+                ((16, 16, 16, 32), SEED_GAUGE + 43), ((16, 16, 16, 32), SEED_GAUGE + 44))
+SERVE_NS = (8, 16, 32)
+SERVE_MQ = (0.01, 0.03, 0.1)
+SERVE_RHS_PER_OPERATOR = 2
+
+
+def serve_operator(field, ns):
+    """Operator of one (field, Ns) pair of the served workload: m0 = 1.8,
+    sigma = omega ~ U[0.5, 1.5] (seeded by Ns), links with eps = 0.5."""
+    dims, seed = SERVE_FIELDS[field]
+    w = uniform_weights(ns, 0.5, 1.5, seed=SEED_GAUGE + 200 + ns)
+    return dict(dims=dims, ns=ns, m0=1.8, sigma=w.copy(), omega=w.copy(), eps=0.5, seed_gauge=seed)
+
+
+def serve_rhs_seed(field, ns, k):
+    return SEED_RHS + 400 + 100 * field + ns + 1000 * k
+
+
+def serve_stream(n, seed=SEED_STREAM):
+    """n requests: field, Ns and mq uniform over their sets, one of
+    SERVE_RHS_PER_OPERATOR right-hand sides, and the gap to the previous
+    arrival as a unit-mean exponential (scaled by 1/rate by the caller)."""
+    rng = _rng(seed)
+    out = []
+    for _ in range(n):
+        out.append(dict(field=int(rng.integers(0, len(SERVE_FIELDS))),
+                        ns=SERVE_NS[int(rng.integers(0, len(SERVE_NS)))],
+                        mq=SERVE_MQ[int(rng.integers(0, len(SERVE_MQ)))],
+                        rhs=int(rng.integers(0, SERVE_RHS_PER_OPERATOR)),
+                        gap=float(rng.exponential(1.0))))
+    return out

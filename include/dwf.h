@@ -108,7 +108,7 @@ typedef struct dwf_solve_stats {
     int restarts;            /* outer high-precision residual recomputations              */
     int reliable_updates;    /* restarts taken in reliable-update mode (p kept)           */
     int fallback;            /* 1 if the solve switched to defect correction              */
-    int reserved0;
+    int rhs_per_block;       /* right-hand sides per stencil workgroup, tuned per batch   */
     double true_residual;    /* ||b - D x|| / ||b||, FP64 full operator on the GPU        */
     double schur_residual;   /* ||b'' - C y|| / ||b''|| of the final iterate              */
     double seconds;          /* wall time of the solve on the device stream               */

@@ -47,7 +47,7 @@ class SolveParams(ctypes.Structure):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
-                ("reliable_updates", ctypes.c_int), ("fallback", ctypes.c_int), ("reserved0", ctypes.c_int),
+                ("reliable_updates", ctypes.c_int), ("fallback", ctypes.c_int), ("rhs_per_block", ctypes.c_int),
                 ("true_residual", ctypes.c_double), ("schur_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("gflops", ctypes.c_double), ("hbm_gbytes", ctypes.c_double)]
 

@@ -68,9 +68,9 @@ int Workspace::alloc(const std::vector<int>& precs, long V5h, int Ns, int nrhs_)
     return DWF_OK;
 }
 
-int Workspace::alloc_state(int n) {
-    // 6 double arrays + 5 int arrays of length n
-    size_t nd = 6 * (size_t)n, ni = 5 * (size_t)n;
+int Workspace::alloc_state(int n, hipStream_t s) {
+    // 7 double arrays + 4 int arrays of length n
+    size_t nd = 7 * (size_t)n, ni = 4 * (size_t)n;
     int rc = state.alloc(nd * sizeof(double) + ni * sizeof(int));
     if (rc) return rc;
     double* d = state.as<double>();
@@ -81,13 +81,16 @@ int Workspace::alloc_state(int n) {
     st.beta = d + 3 * n;
     st.rr_target = d + 4 * n;
     st.aux = d + 5 * n;
+    st.ecr = d + 6 * n;
     st.live = i;
     st.iters = i + n;
     st.status = i + 2 * n;
     st.maxiter = i + 3 * n;
-    st.emode = i + 4 * n;
-    hipError_t e = hipMemset(state.p, 0, state.bytes);
-    if (e != hipSuccess) return fail(DWF_EDEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
+    // stream-ordered: a legacy-stream operation would conflict with another
+    // thread's graph capture
+    hipError_t e = hipMemsetAsync(state.p, 0, state.bytes, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(DWF_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
     return DWF_OK;
 }
 
@@ -131,8 +134,9 @@ const TableSet* dwf_ctx::table_set(double mq_val, int* rc) {
     for (size_t i = 0; i < n; ++i) h32[i] = (float)ts->host[i];
     if ((*rc = ts->d64.alloc(n * sizeof(double)))) return nullptr;
     if ((*rc = ts->d32.alloc(n * sizeof(float)))) return nullptr;
-    hipError_t e = hipMemcpy(ts->d64.p, ts->host.data(), n * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ts->d32.p, h32.data(), n * sizeof(float), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpyAsync(ts->d64.p, ts->host.data(), n * sizeof(double), hipMemcpyHostToDevice, xfer);
+    if (e == hipSuccess) e = hipMemcpyAsync(ts->d32.p, h32.data(), n * sizeof(float), hipMemcpyHostToDevice, xfer);
+    if (e == hipSuccess) e = hipStreamSynchronize(xfer);
     if (e != hipSuccess) {
         *rc = fail(DWF_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
         return nullptr;
@@ -223,6 +227,7 @@ int dwf_create(dwf_ctx** out, const double* gauge, const int dims[4], int Ns, do
 
     DWF_HIP(hipSetDevice(c->device));
     DWF_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    DWF_HIP(hipStreamCreateWithFlags(&c->xfer, hipStreamNonBlocking));
     int rc;
     const size_t nl = (size_t)c->V4h * 8;
     for (int par = 0; par < 2; ++par) {
@@ -249,59 +254,83 @@ void dwf_destroy(dwf_ctx* c) {
     server_detach(c);
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    hipStream_t s = c->stream;
+    hipStream_t s = c->stream, x = c->xfer;
     delete c;
     if (s) (void)hipStreamDestroy(s);
+    if (x) (void)hipStreamDestroy(x);
 }
 
-int dwf_apply_dev(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs, void* stream) {
-    g_err.clear();
-    if (!c || !in_dev || !out_dev) return fail(DWF_EINVAL, "NULL context or buffer");
+}  // extern "C"
+
+namespace {
+
+int check_apply(dwf_ctx* c, int op, int prec, const void* in, const void* out, int nrhs) {
+    if (!c || !in || !out) return fail(DWF_EINVAL, "NULL context or buffer");
     if (op < DWF_OP_DW || op > DWF_OP_DDAG) return fail(DWF_EINVAL, "unknown operator");
     if (prec < DWF_PREC_FP64 || prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "unknown precision");
     if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
+    return DWF_OK;
+}
+
+int check_solve(dwf_ctx* c, const void* b, const void* x, int nrhs, const dwf_solve_params* params,
+                dwf_solve_params* p) {
+    if (!c || !b || !x) return fail(DWF_EINVAL, "NULL context or buffer");
+    if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
+    if (params)
+        *p = *params;
+    else
+        dwf_default_params(p);
+    if (!(p->tol > 0)) return fail(DWF_EINVAL, "tol must be > 0");
+    if (p->inner_prec < DWF_PREC_FP64 || p->inner_prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "bad inner_prec");
+    if (p->maxiter < 1) return fail(DWF_EINVAL, "maxiter must be >= 1");
+    if (p->link_compress < -1 || p->link_compress > 1) return fail(DWF_EINVAL, "link_compress must be -1, 0 or 1");
+    return DWF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dwf_apply_dev(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs, void* stream) {
+    g_err.clear();
+    int rc = check_apply(c, op, prec, in_dev, out_dev, nrhs);
+    if (rc) return rc;
     std::lock_guard<std::mutex> lk(c->mtx);
     DWF_HIP(hipSetDevice(c->device));
     hipStream_t s = stream ? (hipStream_t)stream : c->stream;
-    int rc = apply_op(c, op, prec, in_dev, out_dev, nrhs, s);
-    if (rc) return rc;
+    if ((rc = apply_op(c, op, prec, in_dev, out_dev, nrhs, s))) return rc;
     DWF_HIP(hipStreamSynchronize(s));
     return DWF_OK;
 }
 
+// The host-pointer forms copy on the context's stream (never the legacy
+// stream, which would conflict with the request server's graph captures).
 int dwf_apply(dwf_ctx* c, int op, int prec, const double* in, double* out, int nrhs) {
     g_err.clear();
-    if (!c || !in || !out) return fail(DWF_EINVAL, "NULL context or buffer");
-    if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
-    size_t n = (size_t)nrhs * c->V4 * c->Ns * 24 * sizeof(double);
-    DWF_HIP(hipSetDevice(c->device));
-    DevBuf din, dout;
-    int rc;
-    if ((rc = din.alloc(n)) || (rc = dout.alloc(n))) return rc;
-    DWF_HIP(hipMemcpy(din.p, in, n, hipMemcpyHostToDevice));
-    rc = dwf_apply_dev(c, op, prec, din.as<double>(), dout.as<double>(), nrhs, nullptr);
+    int rc = check_apply(c, op, prec, in, out, nrhs);
     if (rc) return rc;
-    DWF_HIP(hipMemcpy(out, dout.p, n, hipMemcpyDeviceToHost));
+    const size_t n = (size_t)nrhs * c->V4 * c->Ns * 24 * sizeof(double);
+    std::lock_guard<std::mutex> lk(c->mtx);
+    DWF_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    DevBuf din, dout;
+    if ((rc = din.alloc(n)) || (rc = dout.alloc(n))) return rc;
+    DWF_HIP(hipMemcpyAsync(din.p, in, n, hipMemcpyHostToDevice, s));
+    if ((rc = apply_op(c, op, prec, din.as<double>(), dout.as<double>(), nrhs, s))) return rc;
+    DWF_HIP(hipMemcpyAsync(out, dout.p, n, hipMemcpyDeviceToHost, s));
+    DWF_HIP(hipStreamSynchronize(s));
     return DWF_OK;
 }
 
 int dwf_solve_dev(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params* params,
                   dwf_solve_stats* stats, void* stream) {
     g_err.clear();
-    if (!c || !b_dev || !x_dev) return fail(DWF_EINVAL, "NULL context or buffer");
-    if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
     dwf_solve_params p;
-    if (params)
-        p = *params;
-    else
-        dwf_default_params(&p);
-    if (!(p.tol > 0)) return fail(DWF_EINVAL, "tol must be > 0");
-    if (p.inner_prec < DWF_PREC_FP64 || p.inner_prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "bad inner_prec");
-    if (p.maxiter < 1) return fail(DWF_EINVAL, "maxiter must be >= 1");
+    int rc = check_solve(c, b_dev, x_dev, nrhs, params, &p);
+    if (rc) return rc;
     std::lock_guard<std::mutex> lk(c->mtx);
     DWF_HIP(hipSetDevice(c->device));
     hipStream_t s = stream ? (hipStream_t)stream : c->stream;
-    if (p.link_compress < -1 || p.link_compress > 1) return fail(DWF_EINVAL, "link_compress must be -1, 0 or 1");
     return solve(c, b_dev, x_dev, nrhs, p, stats, s);
 }
 
@@ -323,18 +352,23 @@ int dwf_time_kernels(dwf_ctx* c, const dwf_solve_params* params, int nrhs, int l
 int dwf_solve(dwf_ctx* c, const double* b, double* x, int nrhs, const dwf_solve_params* params,
               dwf_solve_stats* stats) {
     g_err.clear();
-    if (!c || !b || !x) return fail(DWF_EINVAL, "NULL context or buffer");
-    if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
-    size_t n = (size_t)nrhs * c->V4 * c->Ns * 24 * sizeof(double);
+    dwf_solve_params p;
+    int rc = check_solve(c, b, x, nrhs, params, &p);
+    if (rc) return rc;
+    const size_t n = (size_t)nrhs * c->V4 * c->Ns * 24 * sizeof(double);
+    std::lock_guard<std::mutex> lk(c->mtx);
     DWF_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
     DevBuf db, dx;
-    int rc;
     if ((rc = db.alloc(n)) || (rc = dx.alloc(n))) return rc;
-    DWF_HIP(hipMemcpy(db.p, b, n, hipMemcpyHostToDevice));
-    if (params && params->use_guess) DWF_HIP(hipMemcpy(dx.p, x, n, hipMemcpyHostToDevice));
-    rc = dwf_solve_dev(c, db.as<double>(), dx.as<double>(), nrhs, params, stats, nullptr);
+    DWF_HIP(hipMemcpyAsync(db.p, b, n, hipMemcpyHostToDevice, s));
+    if (p.use_guess) DWF_HIP(hipMemcpyAsync(dx.p, x, n, hipMemcpyHostToDevice, s));
+    rc = solve(c, db.as<double>(), dx.as<double>(), nrhs, p, stats, s);
     if (rc != DWF_OK && rc != DWF_ENOCONV) return rc;
-    DWF_HIP(hipMemcpy(x, dx.p, n, hipMemcpyDeviceToHost));
+    const std::string msg = dwf_last_error();
+    DWF_HIP(hipMemcpyAsync(x, dx.p, n, hipMemcpyDeviceToHost, s));
+    DWF_HIP(hipStreamSynchronize(s));
+    if (rc) fail(rc, msg);
     return rc;
 }
 

@@ -98,7 +98,7 @@ struct Workspace {
     HalfField& f(int i) { return *fields[i]; }
     // allocate n fields: precs[i] for field i
     int alloc(const std::vector<int>& precs, long V5h, int Ns, int nrhs_);
-    int alloc_state(int nrhs_);
+    int alloc_state(int nrhs_, hipStream_t s);
 };
 
 // Phases of one right-hand side ("slot") of a solve engine.
@@ -122,6 +122,7 @@ class EngineBase {
   public:
     virtual ~EngineBase() {}
     virtual int capacity() const = 0;
+    virtual int rhs_per_block() const = 0;  // tuned right-hand sides per stencil workgroup
     virtual int phase(int slot) const = 0;
     virtual int busy() const = 0;  // slots not free
     virtual int pending() const = 0;  // slots neither free nor done
@@ -139,6 +140,7 @@ class EngineBase {
     virtual int retire(int slot, double* x_dev, SlotResult* res) = 0;
     virtual int time_kernels(int launches, double* ms, double* bytes) = 0;
     virtual size_t device_bytes() const = 0;
+    virtual void report() = 0;  // time accounting to stderr when DWF_VERBOSE is set
 };
 
 int make_engine(dwf_ctx* c, const dwf_solve_params& p, int K, hipStream_t s, std::unique_ptr<EngineBase>* out);
@@ -156,6 +158,8 @@ struct dwf_ctx {
     dwf_opts opts;
     int device;
     hipStream_t stream = nullptr;
+    hipStream_t xfer = nullptr;  // table uploads (never a legacy-stream operation: other
+                                 // threads may be capturing graphs)
     long V4, V4h, V5h;
     int G64, G32;  // 4D sites per workgroup for FP64 and FP32/FP16 kernels
     dwf::DevBuf links[2][dwf::LINK_NFMT];  // [output parity][format]
@@ -181,21 +185,57 @@ namespace dwf {
 
 inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
+// Explicit graph construction.  While a GraphBuilder is active on a thread,
+// the launch helpers append kernel nodes (each depending on the previous one)
+// instead of launching.  No stream is captured, so other threads keep full use
+// of the device (HIP refuses legacy-stream work while any stream captures).
+struct GraphBuilder {
+    hipGraph_t graph = nullptr;
+    hipGraphNode_t last = nullptr;
+    hipError_t err = hipSuccess;
+};
+inline thread_local GraphBuilder* tl_builder = nullptr;
+
+template <class... Args>
+hipError_t launch_kernel(void (*kern)(Args...), dim3 grid, dim3 block, size_t smem, hipStream_t st,
+                         Args... args) {
+    GraphBuilder* b = tl_builder;
+    if (!b) {
+        hipLaunchKernelGGL(kern, grid, block, smem, st, args...);
+        return hipGetLastError();
+    }
+    if (b->err != hipSuccess) return b->err;
+    void* params[] = {(void*)&args...};  // values are copied into the node
+    hipKernelNodeParams kp{};
+    kp.func = (void*)kern;
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = (unsigned)smem;
+    kp.kernelParams = params;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    b->err = hipGraphAddKernelNode(&node, b->graph, b->last ? &b->last : nullptr, b->last ? 1 : 0, &kp);
+    if (b->err == hipSuccess) b->last = node;
+    return b->err;
+}
+
 template <class Real, class F, class LF, bool HOP, int MIXM, class Pro, class Epi>
 hipError_t launch_dwf(const Geom& g, const F& in, const LF& links, const Real* table, const Pro& pro,
                       const Epi& epi, KOpt o, hipStream_t st) {
     int T = round_up(g.G * g.Ns, 64);
     size_t sm = kernel_smem<Real>(g.G, g.Ns, HOP, MIXM != MIX_NONE);
+    const int rpb = o.rpb > 0 && o.rpb < o.nrhs ? o.rpb : o.nrhs;
+    o.rpb = rpb;
+    const unsigned ng = o.ngroups > 0 ? (unsigned)o.ngroups : (unsigned)((o.nrhs + rpb - 1) / rpb);
+    const dim3 grid((unsigned)g.nblocks * ng), block(T);
     if (g.Ns <= 8)
-        hipLaunchKernelGGL((k_dwf<Real, F, LF, 8, HOP, MIXM, Pro, Epi>), dim3(g.nblocks), dim3(T), sm, st, g, in,
-                           links, table, pro, epi, o);
-    else if (g.Ns <= 16)
-        hipLaunchKernelGGL((k_dwf<Real, F, LF, 16, HOP, MIXM, Pro, Epi>), dim3(g.nblocks), dim3(T), sm, st, g, in,
-                           links, table, pro, epi, o);
-    else
-        hipLaunchKernelGGL((k_dwf<Real, F, LF, 32, HOP, MIXM, Pro, Epi>), dim3(g.nblocks), dim3(T), sm, st, g, in,
-                           links, table, pro, epi, o);
-    return hipGetLastError();
+        return launch_kernel(k_dwf<Real, F, LF, 8, HOP, MIXM, Pro, Epi>, grid, block, sm, st, g, in, links, table,
+                             pro, epi, o);
+    if (g.Ns <= 16)
+        return launch_kernel(k_dwf<Real, F, LF, 16, HOP, MIXM, Pro, Epi>, grid, block, sm, st, g, in, links, table,
+                             pro, epi, o);
+    return launch_kernel(k_dwf<Real, F, LF, 32, HOP, MIXM, Pro, Epi>, grid, block, sm, st, g, in, links, table, pro,
+                         epi, o);
 }
 
 // finish kernel modes

@@ -567,6 +567,11 @@ struct KOpt {
     double* partials;      // [nrhs][nblocks] block sums when the epilogue reduces
     int nrhs;
     long table_rstride;    // elements between right-hand sides' tables (0 = shared)
+    int rpb;               // right-hand sides per workgroup (0 = all): the grid holds
+                           // nblocks x ngroups workgroups, group-major
+    const int* glist;      // NULL: right-hand sides 0..nrhs-1; else glist[0] = n and
+                           // glist[1..n] the right-hand sides the grid covers
+    int ngroups;           // groups in the grid (0 = ceil(nrhs / rpb))
 };
 
 template <class Real>
@@ -598,9 +603,18 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
     const int Ns = g.Ns;
     const int tid = threadIdx.x, T = blockDim.x;
 
-    if (o.live) {  // uniform early exit when no right-hand side is live
+    // workgroup -> (group of right-hand sides, lattice block)
+    const int L = xcd_remap(blockIdx.x, gridDim.x, g.xcd);
+    const int grp = L / g.nblocks;
+    const int lb = L - grp * g.nblocks;
+    const int rpb = o.rpb > 0 ? o.rpb : o.nrhs;
+    const int nsel = o.glist ? o.glist[0] : o.nrhs;
+    const int j0 = grp * rpb, j1 = min(nsel, j0 + rpb);
+    auto rhs_of = [&](int j) { return o.glist ? o.glist[1 + j] : j; };
+
+    if (o.live) {  // uniform early exit when no right-hand side of the group is live
         int any = 0;
-        for (int r = 0; r < o.nrhs; ++r) any |= o.live[r];
+        for (int j = j0; j < j1; ++j) any |= o.live[rhs_of(j)];
         if (!any) return;
     }
 
@@ -611,7 +625,6 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
     off = (off + 15) & ~(size_t)15;
     double* red = (double*)(smem + off);
 
-    const int lb = xcd_remap(blockIdx.x, g.nblocks, g.xcd);
     const long site0 = (long)lb * g.G;
     const int nsites = (int)min((long)g.G, (long)g.V4h - site0);
     const int sl = tid / Ns, s = tid - sl * Ns;
@@ -648,7 +661,8 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
         }
     }
 
-    for (int rhs = 0; rhs < o.nrhs; ++rhs) {
+    for (int j = j0; j < j1; ++j) {
+        const int rhs = rhs_of(j);
         if (o.live && !o.live[rhs]) continue;
         Real v[24];
         if (act) {
@@ -697,7 +711,7 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
         if (act) part = epi(rhs, i5, s, v);
         if constexpr (Epi::kReduce) {
             double tot = block_sum(part, red);
-            if (tid == 0) o.partials[(long)rhs * gridDim.x + blockIdx.x] = tot;
+            if (tid == 0) o.partials[(long)rhs * g.nblocks + lb] = tot;
         }
         if constexpr (MIX) __syncthreads();
     }
@@ -714,12 +728,13 @@ struct CgState {
     double* beta;
     double* rr_target;  // the inner solve stops once rr <= rr_target
     double* aux;        // generic reduction results
+    double* ecr;        // coefficient of r in the next direction update (kernel E)
     int* live;          // 1 while the inner solve runs
     int* iters;         // inner iterations done (all cycles)
     int* status;        // 0 running, 1 converged, 2 breakdown, 3 iteration cap, 4 diverged
     int* maxiter;
-    int* emode;         // direction update of the next kernel E: 0 p = r + beta p, 1 p = r
-                        // (fresh Krylov space), 2 p kept; cleared once E has run
+    int* live_host;     // mapped pinned host copy of live (NULL = none), written when a
+                        // right-hand side stops, so the host sees it without a copy
 };
 
 // ---------------------------------------------------------------------------
@@ -733,30 +748,25 @@ struct ProLoad {
     __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const { f.load(rhs, i, s, v); }
 };
 
-// CG direction update, Algorithm 1: p = r + beta p.  With a per-right-hand-
-// side mode (emode, NULL = 0): 1 restarts from p = r, 2 keeps p as it is (the
-// reliable-update restart), so the kernel only forms M5^T gamma_5 p.
+// CG direction update, Algorithm 1: p = c_r r + beta p with a per-right-hand-
+// side c_r (NULL = 1).  After every iteration c_r = 1 and beta is CG's; a
+// restart sets (c_r, beta) = (1, 0) on a zeroed p (fresh Krylov space) or
+// (0, 1) (reliable update: p kept, only M5^T gamma_5 p is formed).
 template <class FR, class FP>
 struct ProCgE {
     FR r;
     FP p;
     const double* beta;
-    const int* emode;
+    const double* ecr;
     template <class Real>
     __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const {
-        const int m = emode ? emode[rhs] : 0;
-        if (m == 2) {
-            p.load(rhs, i, s, v);
-            return;
-        }
         r.load(rhs, i, s, v);
-        if (m == 0) {
-            Real b = (Real)beta[rhs];
-            Real q[24];
-            p.load(rhs, i, s, q);
+        const Real a = ecr ? (Real)ecr[rhs] : (Real)1;
+        const Real b = (Real)beta[rhs];
+        Real q[24];
+        p.load(rhs, i, s, q);
 #pragma unroll
-            for (int k = 0; k < 24; ++k) v[k] += b * q[k];
-        }
+        for (int k = 0; k < 24; ++k) v[k] = a * v[k] + b * q[k];
         p.store(rhs, i, s, v);
     }
 };

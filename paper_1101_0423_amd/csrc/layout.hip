@@ -185,10 +185,10 @@ __global__ void k_finish(const double* __restrict__ partials, int nblocks, int n
                 st.rr[r] = tot;
             } else if (mode == FIN_ALPHA) {
                 st.uu[r] = tot;
-                st.emode[r] = 0;  // kernel E of this iteration has consumed it
                 if (!(tot > 0.0) || !isfinite(tot)) {
                     st.status[r] = 2;
                     st.live[r] = 0;
+                    if (st.live_host) st.live_host[r] = 0;
                 } else {
                     st.alpha[r] = st.rr[r] / tot;
                 }
@@ -196,8 +196,10 @@ __global__ void k_finish(const double* __restrict__ partials, int nblocks, int n
                 if (!isfinite(tot)) {
                     st.status[r] = 2;
                     st.live[r] = 0;
+                    if (st.live_host) st.live_host[r] = 0;
                 } else {
                     st.beta[r] = tot / st.rr[r];
+                    st.ecr[r] = 1.0;
                     st.rr[r] = tot;
                     st.iters[r] += 1;
                     if (tot <= st.rr_target[r]) {
@@ -210,6 +212,7 @@ __global__ void k_finish(const double* __restrict__ partials, int nblocks, int n
                         st.live[r] = 0;
                         st.status[r] = 3;
                     }
+                    if (st.live_host && !st.live[r]) st.live_host[r] = 0;
                 }
             }
         }
@@ -221,8 +224,7 @@ __global__ void k_finish(const double* __restrict__ partials, int nblocks, int n
 
 hipError_t launch_finish(const double* partials, int nblocks, int nrhs, CgState st, int mode, hipStream_t s,
                          const int* mask) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, partials, nblocks, nrhs, st, mode, mask);
-    return hipGetLastError();
+    return launch_kernel(k_finish, dim3(1), dim3(256), 0, s, partials, nblocks, nrhs, st, mode, mask);
 }
 
 hipError_t host_to_half(const dwf_ctx* c, const double* host, int nrhs, HalfField& even, HalfField& odd,

@@ -17,8 +17,9 @@
 //   C: t3 = M5 D^EO u                                       (even)
 //   D: q  = u - M5 D^OE t3;  y += alpha u;  r -= alpha q;  |r|^2 (odd) -> beta
 // alpha, beta and the convergence flags never leave the device; the host
-// replays a captured hipGraph of several iterations and reads the state back
-// between replays.
+// replays a hipGraph of four iterations and watches the live flags that the
+// finisher mirrors into mapped host memory, so that a round of replays ends
+// when a right-hand side ends its cycle.
 //
 // The engine runs K right-hand sides ("slots") through these kernels at once:
 // every kernel reads each gauge link once for all live slots.  Each slot has
@@ -34,6 +35,7 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 #include <vector>
 
 #include "dwf_ctx.h"
@@ -70,7 +72,8 @@ namespace {
 enum { B_E = 0, B_O, BP_E, BP_O, BPP, YH_E, YH_O, T64_E, NF64 };
 enum { L_R = NF64, L_P, L_U, L_T1, L_T23, L_Y, NFALL };
 // per-slot masks on the device (each has its own pinned staging row)
-enum { M_SETUP = 0, M_GUESS, M_NOGUESS, M_OUTER, M_REVERT, M_RUFIN, M_POST, M_FINAL, M_AGAIN, NMASK };
+enum { M_SETUP = 0, M_GUESS, M_NOGUESS, M_OUTER, M_REVERT, M_RESET, M_RUFIN, M_POST, M_FINAL, M_AGAIN, NMASK };
+enum { LIST_INNER = 0, LIST_RUFIN, NLIST };
 
 constexpr int kItersPerGraph = 4;
 
@@ -89,9 +92,6 @@ struct SlotCtl {
     int failed = 0, round = 0, restarts = 0, stuck = 0;
     double rhat_prev = 0, tol_schur = 0, true_res = 0, schur_res = 0, bnorm2 = 0, bpp2 = 0;
     double eps_dc = 0, eps_ru = 0;
-    // convergence-rate bookkeeping for the replay count
-    double rr_last = -1, rate = 0;
-    int it_last = 0, probe = 1;
     std::chrono::steady_clock::time_point t0;
     double seconds = 0;
 };
@@ -104,6 +104,13 @@ class Engine : public EngineBase {
           lk64{LinkD18{c_->links[0][LINK_D18].as<double>()}, LinkD18{c_->links[1][LINK_D18].as<double>()}},
           sl((size_t)K_) {}
     ~Engine() override {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        if (ev[1]) (void)hipEventDestroy(ev[1]);
+        if (live_pin) (void)hipHostFree(live_pin);
+        for (auto& kv : graphs) {
+            (void)hipGraphExecDestroy(kv.second.second);
+            (void)hipGraphDestroy(kv.second.first);
+        }
         if (pin) (void)hipHostFree(pin);
     }
 
@@ -112,24 +119,35 @@ class Engine : public EngineBase {
         std::vector<int> precs(NF64, DWF_PREC_FP64);
         for (int i = 0; i < 5; ++i) precs.push_back(prec);
         precs.push_back(prec == DWF_PREC_FP64 ? DWF_PREC_FP64 : DWF_PREC_FP32);  // y
-        if ((rc = w.alloc(precs, c->V5h, c->Ns, K)) || (rc = w.alloc_state(K))) return rc;
+        if ((rc = w.alloc(precs, c->V5h, c->Ns, K)) || (rc = w.alloc_state(K, s))) return rc;
+        // live flags mirrored by the finisher into mapped host memory
+        DWF_HIP(hipHostMalloc(&live_pin, (size_t)K * sizeof(int), hipHostMallocMapped));
+        memset(live_pin, 0, (size_t)K * sizeof(int));
+        DWF_HIP(hipHostGetDevicePointer((void**)&w.st.live_host, live_pin, 0));
+        DWF_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        DWF_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
         TS = (long)tables_size(c->Ns);
         if ((rc = tabs64.alloc((size_t)TS * K * sizeof(double))) || (rc = tabs32.alloc((size_t)TS * K * sizeof(float))))
             return rc;
         nbmax = std::max(c->geom(0, true).nblocks, c->geom(0, false).nblocks);
-        if ((rc = aux.alloc((size_t)nbmax * K * sizeof(double) + (size_t)NMASK * K * sizeof(int)))) return rc;
+        if ((rc = aux.alloc((size_t)nbmax * K * sizeof(double) + ((size_t)NMASK * K + NLIST * (K + 1)) * sizeof(int))))
+            return rc;
         for (int m = 0; m < NMASK; ++m) dmask[m] = (int*)(aux.as<double>() + (size_t)nbmax * K) + (size_t)m * K;
-        DWF_HIP(hipMemset(aux.p, 0, aux.bytes));
-        const size_t bytes = 6 * (size_t)K * sizeof(double) + (5 + NMASK) * (size_t)K * sizeof(int);
+        for (int l = 0; l < NLIST; ++l) dlist[l] = dmask[0] + (size_t)NMASK * K + (size_t)l * (K + 1);
+        DWF_HIP(hipMemsetAsync(aux.p, 0, aux.bytes, s));
+        DWF_HIP(hipStreamSynchronize(s));
+        const size_t bytes = 7 * (size_t)K * sizeof(double) + ((4 + NMASK) * (size_t)K + NLIST * (K + 1)) * sizeof(int);
         DWF_HIP(hipHostMalloc(&pin, bytes, hipHostMallocDefault));
         memset(pin, 0, bytes);
         hd = (double*)pin;
-        hi = (int*)(hd + 6 * (size_t)K);
-        for (int m = 0; m < NMASK; ++m) hmask[m] = hi + 5 * (size_t)K + (size_t)m * K;
-        return DWF_OK;
+        hi = (int*)(hd + 7 * (size_t)K);
+        for (int m = 0; m < NMASK; ++m) hmask[m] = hi + 4 * (size_t)K + (size_t)m * K;
+        for (int l = 0; l < NLIST; ++l) hlist[l] = hmask[0] + (size_t)NMASK * K + (size_t)l * (K + 1);
+        return autotune();
     }
 
     int capacity() const override { return K; }
+    int rhs_per_block() const override { return kgroup; }
     int phase(int r) const override { return sl[r].phase; }
     int busy() const override {
         int n = 0;
@@ -178,13 +196,20 @@ class Engine : public EngineBase {
 
     int tick() override {
         int rc;
+        using clk = std::chrono::steady_clock;
+        const auto t0 = clk::now();
         if (any(PH_SETUP) && (rc = setup())) return rc;
         for (int guard = 0; any(PH_OUTER) || any(PH_FINAL); ++guard) {
             if (guard > 64) return fail(DWF_EDEVICE, "solve engine: outer loop does not settle");
             if (any(PH_OUTER) && (rc = outer())) return rc;
             if (any(PH_FINAL) && (rc = final_check())) return rc;
         }
+        const auto t1 = clk::now();
         if (any(PH_INNER) && (rc = inner())) return rc;
+        const auto t2 = clk::now();
+        prof.ticks++;
+        prof.outer_s += std::chrono::duration<double>(t1 - t0).count();
+        prof.inner_s += std::chrono::duration<double>(t2 - t1).count();
         return DWF_OK;
     }
 
@@ -214,6 +239,55 @@ class Engine : public EngineBase {
 
     int time_kernels(int launches, double* ms, double* bytes) override;
 
+    // Right-hand sides per workgroup: reading each link once for more of them
+    // saves link bytes, while fewer keep the neighbour re-reads of adjacent
+    // workgroups in L2.  Time one inner iteration (every slot forced on) for
+    // each candidate and keep the fastest.  Runs before any graph capture; the
+    // fields may hold anything, which the solve overwrites before use.
+    int autotune() {
+        kgroup = K;
+        if (K == 1) return DWF_OK;
+        std::vector<int> cand;
+        for (int k : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32})
+            if (k < K) cand.push_back(k);
+        cand.push_back(K);
+        hipEvent_t e0, e1;
+        DWF_HIP(hipEventCreate(&e0));
+        DWF_HIP(hipEventCreate(&e1));
+        double best = 1e30;
+        int bestk = K;
+        hipError_t e = hipSuccess;
+        auto pass = [&]() {
+            hipError_t r = kE(nullptr);
+            if (r == hipSuccess) r = kA(nullptr);
+            if (r == hipSuccess) r = kB(nullptr);
+            if (r == hipSuccess) r = kC(nullptr);
+            if (r == hipSuccess) r = kD(nullptr);
+            return r;
+        };
+        for (int k : cand) {
+            kgroup = k;
+            e = pass();
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int i = 0; i < 2 && e == hipSuccess; ++i) e = pass();
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (getenv("DWF_VERBOSE")) fprintf(stderr, "[dwf] autotune K=%d: %d per workgroup %.3f ms\n", K, k, ms / 2);
+            if (ms < best) {
+                best = ms;
+                bestk = k;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (e != hipSuccess) return fail(DWF_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+        kgroup = bestk;
+        return DWF_OK;
+    }
+
   private:
     dwf_ctx* c;
     int prec, link_fmt, K;
@@ -226,22 +300,50 @@ class Engine : public EngineBase {
     long TS = 0;
     int nbmax = 0;
     int* dmask[NMASK] = {};
+    int* dlist[NLIST] = {};  // compacted slot lists for the inner kernels' grids
+    int* hlist[NLIST] = {};
+    const int* cur_list = nullptr;  // list and group count the inner kernels launch over
+    int cur_ng = 0;
+    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;  // by group count
     void* pin = nullptr;
-    double* hd = nullptr;  // rr, uu, alpha, beta, rr_target, aux  (K each)
-    int* hi = nullptr;     // live, iters, status, maxiter, emode   (K each), then the masks
+    double* hd = nullptr;  // rr, uu, alpha, beta, rr_target, aux, ecr  (K each)
+    int* hi = nullptr;     // live, iters, status, maxiter  (K each), then the masks
     int* hmask[NMASK] = {};
     bool use_graph = true;
-    int replays = 1, replay_cap = 64;
+    int replay_cap = 64;
+    void* live_pin = nullptr;  // host side of st.live_host
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const int verbose = getenv("DWF_VERBOSE") ? atoi(getenv("DWF_VERBOSE")) : 0;
+    int kgroup = 1;  // right-hand sides per workgroup in the inner kernels
+    // host-side accounting of where a solve's time goes (DWF_VERBOSE)
+    struct {
+        long ticks = 0, replays = 0, slot_iters_launched = 0, slot_iters_done = 0;
+        double outer_s = 0, inner_s = 0;
+    } prof;
+
+  public:
+    void report() override {
+        if (!getenv("DWF_VERBOSE")) return;
+        fprintf(stderr,
+                "[dwf] engine K=%d: %ld rounds, %ld graph replays, outer+setup+final %.3f s, inner %.3f s, "
+                "slot iterations done %ld of %ld launched\n",
+                K, prof.ticks, prof.replays, prof.outer_s, prof.inner_s, prof.slot_iters_done,
+                prof.slot_iters_launched);
+        prof = {};
+    }
+
+  private:
 
     // host mirrors
     double& h_rr(int r) { return hd[r]; }
+    double& h_beta(int r) { return hd[3 * K + r]; }
     double& h_target(int r) { return hd[4 * K + r]; }
     double& h_aux(int r) { return hd[5 * K + r]; }
+    double& h_ecr(int r) { return hd[6 * K + r]; }
     int& h_live(int r) { return hi[r]; }
     int& h_iters(int r) { return hi[K + r]; }
     int& h_status(int r) { return hi[2 * K + r]; }
     int& h_maxiter(int r) { return hi[3 * K + r]; }
-    int& h_emode(int r) { return hi[4 * K + r]; }
 
     bool any(int ph) const {
         for (auto& x : sl)
@@ -253,23 +355,28 @@ class Engine : public EngineBase {
     // The host writes a mirror only after a pull (the stream is idle then) and
     // pushes it before the next pull, so the mirrors never race an async copy.
     int pull() {
-        DWF_HIP(hipMemcpyAsync(hd, w.st.rr, 6 * (size_t)K * sizeof(double), hipMemcpyDeviceToHost, s));
-        DWF_HIP(hipMemcpyAsync(hi, w.st.live, 5 * (size_t)K * sizeof(int), hipMemcpyDeviceToHost, s));
+        DWF_HIP(hipMemcpyAsync(hd, w.st.rr, 7 * (size_t)K * sizeof(double), hipMemcpyDeviceToHost, s));
+        DWF_HIP(hipMemcpyAsync(hi, w.st.live, 4 * (size_t)K * sizeof(int), hipMemcpyDeviceToHost, s));
         DWF_HIP(hipStreamSynchronize(s));
         return DWF_OK;
     }
+    // beta, rr_target, aux, ecr and the int state
     int push_ctl() {
-        DWF_HIP(hipMemcpyAsync(w.st.rr_target, &h_target(0), (size_t)K * sizeof(double), hipMemcpyHostToDevice, s));
-        DWF_HIP(hipMemcpyAsync(w.st.live, hi, 5 * (size_t)K * sizeof(int), hipMemcpyHostToDevice, s));
+        DWF_HIP(hipMemcpyAsync(w.st.beta, &h_beta(0), 4 * (size_t)K * sizeof(double), hipMemcpyHostToDevice, s));
+        DWF_HIP(hipMemcpyAsync(w.st.live, hi, 4 * (size_t)K * sizeof(int), hipMemcpyHostToDevice, s));
         return DWF_OK;
     }
+    // Uploads return the number of slots selected; a failed copy is kept in
+    // upload_err and turned into the phase's return code (CKU).
     template <class Pred>
     int upload_mask(int m, Pred pred) {
         int n = 0;
         for (int r = 0; r < K; ++r) n += (hmask[m][r] = pred(r) ? 1 : 0);
-        DWF_HIP(hipMemcpyAsync(dmask[m], hmask[m], (size_t)K * sizeof(int), hipMemcpyHostToDevice, s));
+        hipError_t e = hipMemcpyAsync(dmask[m], hmask[m], (size_t)K * sizeof(int), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess && upload_err == hipSuccess) upload_err = e;
         return n;
     }
+    hipError_t upload_err = hipSuccess;
 
     // ---------------- kernels ----------------
     Geom g64(int par) const { return c->geom(par, true); }
@@ -286,7 +393,29 @@ class Engine : public EngineBase {
             return tabs32.as<float>() + struct_table_offset(c->Ns, t);
     }
     double* part() const { return aux.as<double>(); }
-    KOpt kopt(const int* live, bool red) const { return KOpt{live, red ? part() : nullptr, K, TS}; }
+    // low-precision inner kernels take the tuned group of right-hand sides per
+    // workgroup; the FP64 kernels (outer steps, once per cycle) take them all
+    KOpt kopt(const int* live, bool red) const { return KOpt{live, red ? part() : nullptr, K, TS, 0}; }
+    // Inner kernels launch over a compacted list of slots (cur_list) when one is
+    // set, so that free, finished or waiting slots cost no workgroups.
+    KOpt kopt_in(const int* live, bool red) const {
+        return KOpt{live, red ? part() : nullptr, K, TS, kgroup, cur_list, cur_list ? cur_ng : 0};
+    }
+    // upload the slots that satisfy pred as list l; returns their number
+    template <class Pred>
+    int upload_list(int l, Pred pred) {
+        int n = 0;
+        for (int r = 0; r < K; ++r)
+            if (pred(r)) hlist[l][1 + n++] = r;
+        hlist[l][0] = n;
+        hipError_t e = hipMemcpyAsync(dlist[l], hlist[l], (size_t)(K + 1) * sizeof(int), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess && upload_err == hipSuccess) upload_err = e;
+        return n;
+    }
+    void use_list(int l, int n) {
+        cur_list = dlist[l];
+        cur_ng = (n + kgroup - 1) / kgroup;
+    }
     hipError_t fin(int nblocks, int mode, const int* mask = nullptr) {
         return launch_finish(part(), nblocks, K, w.st, mode, s, mask);
     }
@@ -328,33 +457,33 @@ class Engine : public EngineBase {
     }
 
     // inner CG kernels
-    hipError_t kE(const int* live, const int* emode) {
+    hipError_t kE(const int* live) {
         return launch_dwf<Real, F, LF, false, MIX_AS, ProCgE<F, F>, EpiStore<F>>(
-            glo(1), lo(L_R), lk[1], slo(ST_M5TG5), ProCgE<F, F>{lo(L_R), lo(L_P), w.st.beta, emode},
-            EpiStore<F>{lo(L_T1)}, kopt(live, false), s);
+            glo(1), lo(L_R), lk[1], slo(ST_M5TG5), ProCgE<F, F>{lo(L_R), lo(L_P), w.st.beta, w.st.ecr},
+            EpiStore<F>{lo(L_T1)}, kopt_in(live, false), s);
     }
     hipError_t kA(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_AS, ProLoad<F>, EpiStore<F>>(
-            glo(0), lo(L_T1), lk[0], slo(ST_M5T), ProLoad<F>{lo(L_T1)}, EpiStore<F>{lo(L_T23)}, kopt(live, false), s);
+            glo(0), lo(L_T1), lk[0], slo(ST_M5T), ProLoad<F>{lo(L_T1)}, EpiStore<F>{lo(L_T23)}, kopt_in(live, false), s);
     }
     hipError_t kB(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_NONE, ProLoad<F>, EpiCgB<F, F>>(
-            glo(1), lo(L_T23), lk[1], nullptr, ProLoad<F>{lo(L_T23)}, EpiCgB<F, F>{lo(L_P), lo(L_U)}, kopt(live, true),
+            glo(1), lo(L_T23), lk[1], nullptr, ProLoad<F>{lo(L_T23)}, EpiCgB<F, F>{lo(L_P), lo(L_U)}, kopt_in(live, true),
             s);
     }
     hipError_t kC(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiStore<F>>(
-            glo(0), lo(L_U), lk[0], slo(ST_M5), ProLoad<F>{lo(L_U)}, EpiStore<F>{lo(L_T23)}, kopt(live, false), s);
+            glo(0), lo(L_U), lk[0], slo(ST_M5), ProLoad<F>{lo(L_U)}, EpiStore<F>{lo(L_T23)}, kopt_in(live, false), s);
     }
     hipError_t kD(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiCgD<F, F, FY>>(
             glo(1), lo(L_T23), lk[1], slo(ST_M5), ProLoad<F>{lo(L_T23)},
-            EpiCgD<F, F, FY>{lo(L_U), lo(L_R), ylo(), w.st.alpha}, kopt(live, true), s);
+            EpiCgD<F, F, FY>{lo(L_U), lo(L_R), ylo(), w.st.alpha}, kopt_in(live, true), s);
     }
     hipError_t iteration() {
         hipError_t e;
         const int* live = w.st.live;
-        if ((e = kE(live, w.st.emode)) != hipSuccess) return e;
+        if ((e = kE(live)) != hipSuccess) return e;
         if ((e = kA(live)) != hipSuccess) return e;
         if ((e = kB(live)) != hipSuccess) return e;
         if ((e = fin(glo(1).nblocks, FIN_ALPHA)) != hipSuccess) return e;
@@ -362,20 +491,33 @@ class Engine : public EngineBase {
         if ((e = kD(live)) != hipSuccess) return e;
         return fin(glo(1).nblocks, FIN_BETA);
     }
-    int ensure_graph() {
-        if (w.gexec) return DWF_OK;
-        DWF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    // one graph of kItersPerGraph iterations over cur_list / cur_ng, built
+    // node by node (no stream capture); cached per group count.  The nodes read
+    // the slot list and the CG state on the device, so replays need no update.
+    int graph_for(hipGraphExec_t* out) {
+        auto it = graphs.find(cur_ng);
+        if (it != graphs.end()) {
+            *out = it->second.second;
+            return DWF_OK;
+        }
+        GraphBuilder b;
+        DWF_HIP(hipGraphCreate(&b.graph, 0));
+        tl_builder = &b;
         hipError_t e = hipSuccess;
         for (int i = 0; i < kItersPerGraph && e == hipSuccess; ++i) e = iteration();
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(s, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return fail(DWF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        tl_builder = nullptr;
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(b.graph);
+            return fail(DWF_EDEVICE, std::string("graph build: ") + hipGetErrorString(e));
         }
-        w.graph = g;
-        DWF_HIP(hipGraphInstantiate(&w.gexec, g, nullptr, nullptr, 0));
-        w.graph_iters = kItersPerGraph;
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, b.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(b.graph);
+            return fail(DWF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        graphs[cur_ng] = {b.graph, ex};
+        *out = ex;
         return DWF_OK;
     }
 
@@ -389,11 +531,20 @@ class Engine : public EngineBase {
         int r_ = (x);      \
         if (r_) return r_; \
     } while (0)
+#define CKU()                                                                                                  \
+    do {                                                                                                       \
+        if (upload_err != hipSuccess) {                                                                        \
+            hipError_t e_ = upload_err;                                                                        \
+            upload_err = hipSuccess;                                                                           \
+            return fail(DWF_EDEVICE, std::string("slot mask upload: ") + hipGetErrorString(e_));              \
+        }                                                                                                      \
+    } while (0)
 
     // ---- b -> |b|^2, b' = S1 b, b'' = b'_o - M5 D^OE b'_e, |b''|^2, initial yhat_o
     int setup() {
         int* m = dmask[M_SETUP];
         upload_mask(M_SETUP, [&](int r) { return sl[r].phase == PH_SETUP; });
+        CKU();
         CKE(norm64(0, B_E, m));
         CKE(fin(g64(0).nblocks, FIN_AUX, m));
         CKR(pull());
@@ -405,7 +556,9 @@ class Engine : public EngineBase {
         for (int r = 0; r < K; ++r)
             if (hmask[M_SETUP][r]) sl[r].bnorm2 += h_aux(r);
         int ng = upload_mask(M_GUESS, [&](int r) { return hmask[M_SETUP][r] && sl[r].use_guess; });
+        CKU();
         int nz = upload_mask(M_NOGUESS, [&](int r) { return hmask[M_SETUP][r] && !sl[r].use_guess; });
+        CKU();
         if (ng) CKE(local64(1, BP_O, TB_S2INV, YH_O, dmask[M_GUESS]));
         if (nz) CKE(half_zero(c, w.f(YH_O), K, s, dmask[M_NOGUESS]));
         CKE(local64(0, B_E, TB_S1, BP_E, m));
@@ -421,7 +574,6 @@ class Engine : public EngineBase {
                 h_iters(r) = 0;
                 h_status(r) = 0;
                 h_maxiter(r) = sl[r].p.maxiter;
-                h_emode(r) = 0;
                 h_target(r) = 0;
             }
         return push_ctl();
@@ -431,6 +583,7 @@ class Engine : public EngineBase {
     int outer() {
         int* m = dmask[M_OUTER];
         upload_mask(M_OUTER, [&](int r) { return sl[r].phase == PH_OUTER; });
+        CKU();
         CKE(outer_residual(m));
         for (int r = 0; r < K; ++r)
             if (hmask[M_OUTER][r]) {
@@ -444,6 +597,7 @@ class Engine : public EngineBase {
         int nrev = upload_mask(M_REVERT, [&](int r) {
             return hmask[M_OUTER][r] && sl[r].have_backup && !(sqrt(h_aux(r)) < sl[r].rhat_prev);
         });
+        CKU();
         if (nrev) {
             CKE(half_copy(c, w.f(YH_O), w.f(YH_E), K, dmask[M_REVERT], s));
             CKE(outer_residual(dmask[M_REVERT]));
@@ -509,23 +663,37 @@ class Engine : public EngineBase {
             h_status(r) = 0;
             h_maxiter(r) = q.p.maxiter;
             // p := r on the first cycle, in defect correction and after a
-            // rejected cycle; reliable updates keep p
-            h_emode(r) = (q.cycles == 0 || !q.mode_ru || q.reverted) ? 1 : 2;
+            // rejected cycle (p zeroed below, c_r = 1, beta = 0); reliable
+            // updates keep p (c_r = 0, beta = 1)
+            const bool reset = q.cycles == 0 || !q.mode_ru || q.reverted;
+            h_ecr(r) = reset ? 1.0 : 0.0;
+            h_beta(r) = reset ? 0.0 : 1.0;
+            hmask[M_RESET][r] = reset ? 1 : 0;
             ++q.cycles;
             q.phase = PH_INNER;
-            q.rr_last = -1;
             q.stuck = 0;
             if (getenv("DWF_VERBOSE"))
                 fprintf(stderr, "[dwf] slot %d cycle %d: |rhat|/|b''| = %.3e mode=%s iters=%d%s\n", r, q.cycles,
                         rel, q.mode_ru ? "RU" : "DC", h_iters(r), q.reverted ? " (reverted)" : "");
         }
-        return push_ctl();
+        CKR(push_ctl());
+        int nres = 0;
+        for (int r = 0; r < K; ++r) {
+            if (!(hmask[M_OUTER][r] && sl[r].phase == PH_INNER)) hmask[M_RESET][r] = 0;
+            nres += hmask[M_RESET][r];
+        }
+        if (nres) {
+            DWF_HIP(hipMemcpyAsync(dmask[M_RESET], hmask[M_RESET], (size_t)K * sizeof(int), hipMemcpyHostToDevice, s));
+            CKE(half_zero(c, w.f(L_P), K, s, dmask[M_RESET]));
+        }
+        return DWF_OK;
     }
 
     // ---- reconstruction y_e = b'_e - M5 D^EO y_o, x = S2 y, and |b - D x| / |b|
     int final_check() {
         int* m = dmask[M_FINAL];
         upload_mask(M_FINAL, [&](int r) { return sl[r].phase == PH_FINAL; });
+        CKU();
         CKE(xmy_m5hop64(0, YH_O, BP_E, YH_E, false, m));
         CKE(local64(0, YH_E, TB_S2, BP_E, m));
         CKE(local64(1, YH_O, TB_S2, BP_O, m));
@@ -563,6 +731,7 @@ class Engine : public EngineBase {
         }
         // restore the pieces the reconstruction overwrote: b' and b''
         int na = upload_mask(M_AGAIN, [&](int r) { return hmask[M_FINAL][r] && sl[r].phase == PH_OUTER; });
+        CKU();
         if (na) {
             CKE(local64(0, B_E, TB_S1, BP_E, dmask[M_AGAIN]));
             CKE(local64(1, B_O, TB_S1, BP_O, dmask[M_AGAIN]));
@@ -578,16 +747,55 @@ class Engine : public EngineBase {
         for (int r = 0; r < K; ++r)
             if (sl[r].phase == PH_INNER && sl[r].p.check_every > 0)
                 check = check ? std::min(check, sl[r].p.check_every) : sl[r].p.check_every;
-        int n = check ? std::max(1, (check + kItersPerGraph - 1) / kItersPerGraph) : plan_replays();
-        if (use_graph) {
-            CKR(ensure_graph());
-            for (int k = 0; k < n; ++k) CKE(hipGraphLaunch(w.gexec, s));
-        } else {
-            for (int k = 0; k < n * kItersPerGraph; ++k) CKE(iteration());
+        const int cap = check ? std::max(1, (check + kItersPerGraph - 1) / kItersPerGraph) : replay_cap;
+        const int nl = upload_list(LIST_INNER, [&](int r) { return sl[r].phase == PH_INNER; });
+        CKU();
+        use_list(LIST_INNER, nl);
+        volatile int* lh = (volatile int*)live_pin;
+        for (int r = 0; r < K; ++r) lh[r] = sl[r].phase == PH_INNER ? 1 : 0;
+        hipGraphExec_t ex = nullptr;
+        int rc = use_graph ? graph_for(&ex) : DWF_OK;
+        auto launch_one = [&]() -> int {
+            if (use_graph)
+                return hipGraphLaunch(ex, s) == hipSuccess ? DWF_OK : fail(DWF_EDEVICE, "hipGraphLaunch failed");
+            for (int k = 0; k < kItersPerGraph; ++k)
+                if (iteration() != hipSuccess) return fail(DWF_EDEVICE, "inner iteration launch failed");
+            return DWF_OK;
+        };
+        // Replays until a slot of this round ends its cycle (or the cap): one
+        // replay stays queued while the host checks the mirrored live flags
+        // after the one before it, so a round overruns a slot's end by at
+        // most one replay and the device never waits for the host.
+        int n = 0;
+        while (!rc && n < cap) {
+            if ((rc = launch_one())) break;
+            if (hipEventRecord(ev[n & 1], s) != hipSuccess) rc = fail(DWF_EDEVICE, "hipEventRecord failed");
+            ++n;
+            if (rc || n < 2) continue;
+            if (hipEventSynchronize(ev[n & 1]) != hipSuccess) {  // replay n - 2 is done
+                rc = fail(DWF_EDEVICE, "hipEventSynchronize failed");
+                break;
+            }
+            bool ended = false;
+            for (int r = 0; r < K; ++r) ended |= sl[r].phase == PH_INNER && lh[r] == 0;
+            if (ended) break;
         }
+        cur_list = nullptr;
+        if (rc) return rc;
+        int nlive = 0;
+        for (int r = 0; r < K; ++r) nlive += sl[r].phase == PH_INNER;
+        prof.replays += n;
+        prof.slot_iters_launched += (long)n * kItersPerGraph * nlive;
         std::vector<int> before(K);
         for (int r = 0; r < K; ++r) before[r] = h_iters(r);
         CKR(pull());
+        for (int r = 0; r < K; ++r)
+            if (sl[r].phase == PH_INNER) prof.slot_iters_done += h_iters(r) - before[r];
+        if (verbose >= 2)
+            for (int r = 0; r < K; ++r)
+                if (sl[r].phase == PH_INNER)
+                    fprintf(stderr, "[dwf]   round: %d replays; slot %d iters %d -> %d live=%d rr=%.3e target=%.3e\n",
+                            n, r, before[r], h_iters(r), h_live(r), h_rr(r), h_target(r));
         bool ended = false;
         for (int r = 0; r < K; ++r) {
             if (sl[r].phase != PH_INNER) continue;
@@ -599,35 +807,9 @@ class Engine : public EngineBase {
             // the device stops every slot at maxiter; this only trips if the
             // device state stops advancing
             if (h_iters(r) == before[r] && ++q.stuck >= 3) return fail(DWF_EDEVICE, "inner solve does not advance");
-            // convergence rate per iteration, kept across cycles
-            const double rr = h_rr(r);
-            if (q.rr_last > 0 && h_iters(r) > q.it_last && rr < q.rr_last && rr > 0)
-                q.rate = log(rr / q.rr_last) / (double)(h_iters(r) - q.it_last);
-            q.rr_last = rr;
-            q.it_last = h_iters(r);
         }
         if (ended) CKR(post_cycle());
         return DWF_OK;
-    }
-
-    // graph replays until the first live slot is expected to end its cycle
-    int plan_replays() {
-        double need = 1e30;
-        for (int r = 0; r < K; ++r) {
-            if (sl[r].phase != PH_INNER) continue;
-            SlotCtl& q = sl[r];
-            const double rr = q.rr_last > 0 ? q.rr_last : h_aux(r);
-            double nr;
-            if (q.rate < 0 && rr > 0 && h_target(r) > 0) {
-                nr = std::max(1.0, 0.8 * log(h_target(r) / rr) / q.rate);
-            } else {  // no rate yet: probe with a doubling number of iterations
-                nr = (double)q.probe * kItersPerGraph;
-                q.probe = std::min(64, q.probe * 2);
-            }
-            need = std::min(need, nr);
-        }
-        replays = (int)std::min((double)replay_cap, std::max(1.0, need / kItersPerGraph));
-        return replays;
     }
 
     // the slots whose inner cycle ended: finish p for reliable updates,
@@ -636,10 +818,18 @@ class Engine : public EngineBase {
         int nfin = upload_mask(M_RUFIN, [&](int r) {
             return sl[r].phase == PH_INNER && !h_live(r) && sl[r].mode_ru && h_status(r) == 1;
         });
+        CKU();
         // reliable updates: the last direction update p = r + beta p
         // (Algorithm 1 computes p_{k+1} before testing convergence)
-        if (nfin) CKE(kE(dmask[M_RUFIN], nullptr));
+        if (nfin) {
+            use_list(LIST_RUFIN, upload_list(LIST_RUFIN, [&](int r) { return hmask[M_RUFIN][r] != 0; }));
+            CKU();
+            hipError_t e = kE(dmask[M_RUFIN]);
+            cur_list = nullptr;
+            CKE(e);
+        }
         upload_mask(M_POST, [&](int r) { return sl[r].phase == PH_INNER && !h_live(r); });
+        CKU();
         CKE(half_copy(c, w.f(YH_E), w.f(YH_O), K, dmask[M_POST], s));
         CKE(half_acc(c, w.f(YH_O), w.f(L_Y), K, dmask[M_POST], s));
         for (int r = 0; r < K; ++r) {
@@ -657,6 +847,7 @@ class Engine : public EngineBase {
     }
 #undef CKE
 #undef CKR
+#undef CKU
 };
 
 template <class Real, class F, class FY, class LF>
@@ -665,7 +856,7 @@ int Engine<Real, F, FY, LF>::time_kernels(int launches, double* ms, double* byte
     // update their outputs from finite inputs
     auto runk = [&](int k) -> hipError_t {
         switch (k) {
-            case 0: return kE(nullptr, nullptr);
+            case 0: return kE(nullptr);
             case 1: return kA(nullptr);
             case 2: return kB(nullptr);
             case 3: return kC(nullptr);
@@ -797,6 +988,7 @@ int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_so
     std::vector<SlotResult> res(nrhs);
     for (int r = 0; r < nrhs; ++r)
         if ((rc = eng->retire(r, x_dev + r * n5, &res[r]))) return abandon(rc);
+    eng->report();
     DWF_HIP(hipEventRecord(ev1, s));
     DWF_HIP(hipEventSynchronize(ev1));
     float ms = 0;
@@ -817,6 +1009,7 @@ int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_so
             o.restarts = res[r].restarts;
             o.reliable_updates = res[r].reliable_updates;
             o.fallback = res[r].fallback;
+            o.rhs_per_block = eng->rhs_per_block();
             o.true_residual = res[r].true_residual;
             o.schur_residual = res[r].schur_residual;
             // the batch shares the device: time, rate and bytes are the batch's
