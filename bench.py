@@ -56,7 +56,7 @@ def counter_traffic(kernel, workload):
         return None
 
 
-def cpu_baseline(w, U, b, n1=1, n2=5):
+def cpu_baseline(w, U, b, n1=1, n2=30):
     """The FP64 oracle, as it stands, on the same workload: per-iteration time
     from two bounded runs (n1 and n2 CG iterations)."""
     import oracle
@@ -186,10 +186,11 @@ def batch_bench(args):
     print(json.dumps(line), flush=True)
 
 
-def serve_bench(args):
+def run_serve(n_requests, load, log=True):
     """Poisson stream of independent solves on four resident fields (every
     (field, Ns) pair is one context), served by dwf_submit/dwf_poll, against a
-    FIFO server of plain single-right-hand-side solves on the same stream."""
+    FIFO server of plain single-right-hand-side solves on the same stream.
+    Returns the measurements as a dict."""
     import threading
 
     import numpy as np
@@ -198,8 +199,12 @@ def serve_bench(args):
     import dwf_inputs as inp
     import paper_1101_0423_amd as dwf
 
+    def say(msg):
+        if log:
+            print(msg, file=sys.stderr, flush=True)
+
     torch.cuda.set_device(0)
-    reqs = inp.serve_stream(args.requests)
+    reqs = inp.serve_stream(n_requests)
     used = sorted({(r["field"], r["ns"]) for r in reqs})
     ctxs, rhs, gauges = {}, {}, {}
     for f, ns in used:
@@ -210,7 +215,7 @@ def serve_bench(args):
                                     device=0)
         for k in range(inp.SERVE_RHS_PER_OPERATOR):
             rhs[(f, ns, k)] = inp.gaussian_spinor(o["dims"], ns, seed=inp.serve_rhs_seed(f, ns, k))
-    print(f"[bench] {len(ctxs)} operators resident", file=sys.stderr, flush=True)
+    say(f"[serve] {len(ctxs)} operators resident")
     params = dwf.default_params(inner_prec=1, tol=1e-10)
     # plain single-right-hand-side service time of every request type (a
     # context per mass, so that dwf_solve runs that mass)
@@ -227,10 +232,10 @@ def serve_bench(args):
         x, st, rc = c.solve(b, params=params)
         svc[key] = time.perf_counter() - t0
         c.close()
-        print(f"[bench] service {key}: {svc[key]:.3f}s iters={st[0]['iters']}", file=sys.stderr, flush=True)
+        say(f"[serve] plain service {key}: {svc[key]:.3f}s iters={st[0]['iters']}")
     mean_svc = float(np.mean([svc[(r["field"], r["ns"], r["mq"])] for r in reqs]))
-    if args.load > 0:
-        rate = args.load / mean_svc
+    if load > 0:
+        rate = load / mean_svc
         arrivals = np.cumsum([r["gap"] for r in reqs]) / rate
         arrivals -= arrivals[0]
     else:  # saturated: every request is there at the start
@@ -263,6 +268,7 @@ def serve_bench(args):
     th.start()
     pending = set(range(len(reqs)))
     results = [None] * len(reqs)
+    last_report = time.perf_counter()
     while pending:
         for i in list(pending):
             if tickets[i] is None:
@@ -272,35 +278,48 @@ def serve_bench(args):
             if rc != dwf.DWF_PENDING:
                 results[i] = (rc, st["true_residual"], time.perf_counter() - t_start - arrivals[i])
                 pending.discard(i)
+        if time.perf_counter() - last_report > 10:
+            last_report = time.perf_counter()
+            say(f"[serve] {len(reqs) - len(pending)} of {len(reqs)} requests done")
         time.sleep(0.002)
     span = time.perf_counter() - t_start
     th.join()
     s = dwf.server_stats()
-    ok = all(rc == dwf.DWF_OK for rc, _, _ in results)
     lat = np.array([l for _, _, l in results])
-    line = dict(metric="served solves/s, p99 latency (Poisson stream, 4 resident fields)",
-                value=round(len(reqs) / span, 4), unit="solves/s", n_gpus=1, steps=len(reqs), warmup=len(warm),
-                ms_per_step=round(span / len(reqs) * 1e3, 2), higher_is_better=True, scaling="weak",
-                vs_baseline=None, dtype="f32 inner / f64 outer", data="synthetic",
-                config=dict(workload=f"{len(reqs)} requests, "
-                                     + (f"Poisson arrivals at {args.load} x the plain single-RHS service rate"
-                                        if args.load > 0 else "all submitted at once (saturated)")
-                                     + f"; fields 8^3x16, 12^3x24, 2x 16^3x32 (eps 0.5); "
-                                     f"Ns in {{8,16,32}}, mq in {{0.01,0.03,0.1}}, sigma=omega~U[0.5,1.5], "
-                                     f"Gaussian RHS, tol 1e-10", requests=len(reqs), load=args.load),
+    for c in ctxs.values():
+        c.close()
+    return dict(requests=len(reqs), load=load, solves_per_s=round(len(reqs) / span, 4),
+                solves_per_busy_s=round(s["completed"] / s["busy_seconds"], 4) if s["busy_seconds"] > 0 else None,
                 p50_latency_s=round(s["p50_latency"], 4), p99_latency_s=round(s["p99_latency"], 4),
                 p50_latency_from_arrival_s=round(float(np.percentile(lat, 50)), 4),
                 p99_latency_from_arrival_s=round(float(np.percentile(lat, 99)), 4),
-                peak_batch=s["peak_batch"], waits_for_memory=s["waits_for_memory"], busy_s=round(s["busy_seconds"], 3),
-                fifo=dict(solves_per_s=round(len(reqs) / fifo_span, 4),
+                peak_batch=s["peak_batch"], waits_for_memory=s["waits_for_memory"],
+                busy_s=round(s["busy_seconds"], 3),
+                fifo=dict(solves_per_s=round(len(reqs) / fifo_span, 4), solves_per_busy_s=round(1.0 / mean_svc, 4),
                           p50_latency_s=round(float(np.percentile(fifo_lat, 50)), 4),
                           p99_latency_s=round(float(np.percentile(fifo_lat, 99)), 4),
-                          kind="plain single-RHS solves in arrival order; service times measured per request "
-                               "type on this GPU"),
-                mean_plain_service_s=round(mean_svc, 4), converged=ok,
+                          kind="plain single-RHS solves in arrival order; service time of each request type "
+                               "measured on this GPU"),
+                mean_plain_service_s=round(mean_svc, 4),
+                converged=all(rc == dwf.DWF_OK for rc, _, _ in results),
                 max_true_residual=max(r for _, r, _ in results))
-    for c in ctxs.values():
-        c.close()
+
+
+SERVE_WORKLOAD = ("fields 8^3x16, 12^3x24, 2x 16^3x32 (eps 0.5); per request Ns in {8,16,32}, "
+                  "mq in {0.01,0.03,0.1}, sigma=omega~U[0.5,1.5], m0=1.8, Gaussian RHS, tol 1e-10")
+
+
+def serve_bench(args):
+    r = run_serve(args.requests, args.load)
+    arrivals = (f"Poisson arrivals at {args.load} x the plain single-RHS service rate" if args.load > 0
+                else "all submitted at once (saturated)")
+    line = dict(metric="served solves/s, p99 latency (Poisson stream, 4 resident fields)",
+                value=r["solves_per_s"], unit="solves/s", n_gpus=1, steps=r["requests"], warmup=0,
+                ms_per_step=round(1e3 / r["solves_per_s"], 2), higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="f32 inner / f64 outer", data="synthetic",
+                config=dict(workload=f"{r['requests']} requests, {arrivals}; {SERVE_WORKLOAD}",
+                            requests=r["requests"], load=args.load), **{k: v for k, v in r.items()
+                                                                         if k not in ("requests", "load")})
     print(json.dumps(line), flush=True)
 
 
@@ -318,6 +337,8 @@ def main():
                          "batched vs sequential; serve: Poisson request stream, served vs FIFO")
     ap.add_argument("--nrhs", type=int, default=12, help="batch mode: right-hand sides")
     ap.add_argument("--requests", type=int, default=200, help="serve mode: requests in the stream")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="solve mode: requests of the served stream measured after the solves (0: none)")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serve mode: arrival rate / plain service rate (0: all requests at once)")
     ap.add_argument("--summarize-rocpd", metavar="DB", help="print per-kernel statistics of a rocprofv3 "
@@ -403,10 +424,15 @@ def main():
                 hbm_gbs=round(gbytes / elapsed, 1), iters=stats[-1][0]["iters"],
                 true_residual=stats[-1][0]["true_residual"], converged=ok,
                 roofline=roofline, kernels=kernels)
+    ctx.close()
+    if args.serve_requests > 0:
+        print(f"[bench] served stream of {args.serve_requests} requests", file=sys.stderr, flush=True)
+        sv = run_serve(args.serve_requests, 0.8)
+        line["served"] = dict(workload=f"{sv['requests']} requests, Poisson arrivals at 0.8 x the plain "
+                                       f"single-RHS service rate; {SERVE_WORKLOAD}", **sv)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, U, b)
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

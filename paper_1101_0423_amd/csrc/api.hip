@@ -156,6 +156,31 @@ int dwf_ctx::ensure_partials(size_t n) {
     return DWF_OK;
 }
 
+namespace {
+
+std::mutex g_links_mu;
+std::map<std::string, std::weak_ptr<LinkSet>> g_links;  // resident fields by content
+
+// Two independent 64-bit hashes of the field's words, with its extents and
+// device: contexts on the same field find each other's links.
+std::string gauge_key(const double* gauge, const int dims[4], int device) {
+    const size_t n = (size_t)dims[0] * dims[1] * dims[2] * dims[3] * 4 * 18;
+    uint64_t h1 = 0xcbf29ce484222325ull, h2 = 0x9e3779b97f4a7c15ull;
+    for (size_t i = 0; i < n; ++i) {
+        uint64_t w;
+        memcpy(&w, gauge + i, sizeof(w));
+        h1 = (h1 ^ w) * 0x100000001b3ull;
+        h2 = (h2 + w) * 0xff51afd7ed558ccdull;
+        h2 ^= h2 >> 33;
+    }
+    char buf[128];
+    snprintf(buf, sizeof(buf), "%d:%dx%dx%dx%d:%016llx%016llx", device, dims[0], dims[1], dims[2], dims[3],
+             (unsigned long long)h1, (unsigned long long)h2);
+    return buf;
+}
+
+}  // namespace
+
 extern "C" {
 
 void dwf_default_opts(dwf_opts* o) {
@@ -229,19 +254,34 @@ int dwf_create(dwf_ctx** out, const double* gauge, const int dims[4], int Ns, do
     DWF_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     DWF_HIP(hipStreamCreateWithFlags(&c->xfer, hipStreamNonBlocking));
     int rc;
-    const size_t nl = (size_t)c->V4h * 8;
-    for (int par = 0; par < 2; ++par) {
-        if ((rc = c->links[par][LINK_D18].alloc(nl * 18 * sizeof(double)))) return rc;
-        if ((rc = c->links[par][LINK_S18].alloc(nl * 18 * sizeof(float)))) return rc;
-        if ((rc = c->links[par][LINK_S12].alloc(nl * 12 * sizeof(float)))) return rc;
-        if ((rc = c->links[par][LINK_H12].alloc(nl * 12 * sizeof(_Float16)))) return rc;
-    }
     {
-        DevBuf g;
-        if ((rc = g.alloc((size_t)V4 * 4 * 18 * sizeof(double)))) return rc;
-        DWF_HIP(hipMemcpyAsync(g.p, gauge, (size_t)V4 * 4 * 18 * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        DWF_HIP(pack_links(c.get(), g.as<double>(), c->stream));
-        DWF_HIP(hipStreamSynchronize(c->stream));
+        // share the resident links of an identical field
+        const std::string key = gauge_key(gauge, dims, c->device);
+        std::lock_guard<std::mutex> lk(g_links_mu);
+        auto it = g_links.find(key);
+        if (it != g_links.end()) c->lset = it->second.lock();
+        if (!c->lset) {
+            std::shared_ptr<LinkSet> ls(new LinkSet);
+            c->lset = ls;
+            c->links = ls->buf;
+            const size_t nl = (size_t)c->V4h * 8;
+            for (int par = 0; par < 2; ++par) {
+                if ((rc = ls->buf[par][LINK_D18].alloc(nl * 18 * sizeof(double)))) return rc;
+                if ((rc = ls->buf[par][LINK_S18].alloc(nl * 18 * sizeof(float)))) return rc;
+                if ((rc = ls->buf[par][LINK_S12].alloc(nl * 12 * sizeof(float)))) return rc;
+                if ((rc = ls->buf[par][LINK_H12].alloc(nl * 12 * sizeof(_Float16)))) return rc;
+            }
+            DevBuf g;
+            if ((rc = g.alloc((size_t)V4 * 4 * 18 * sizeof(double)))) return rc;
+            DWF_HIP(hipMemcpyAsync(g.p, gauge, (size_t)V4 * 4 * 18 * sizeof(double), hipMemcpyHostToDevice,
+                                   c->stream));
+            DWF_HIP(pack_links(c.get(), g.as<double>(), c->stream));
+            DWF_HIP(hipStreamSynchronize(c->stream));
+            for (auto i = g_links.begin(); i != g_links.end();) i = i->second.expired() ? g_links.erase(i) : ++i;
+            g_links[key] = ls;
+        }
+        c->links = c->lset->buf;
+        c->gauge_key = key;
     }
     c->table_set(mq, &rc);
     if (rc) return rc;

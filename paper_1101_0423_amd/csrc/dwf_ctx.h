@@ -53,6 +53,14 @@ struct DevBuf {
 // Link formats held per parity.
 enum LinkFmt { LINK_D18 = 0, LINK_S18 = 1, LINK_S12 = 2, LINK_H12 = 3, LINK_NFMT = 4 };
 
+// The packed gauge links of one field in every format, per output parity.
+// Contexts built on the same field (same content, extents and device) share
+// one LinkSet: the links do not depend on Ns, the masses or the boundary
+// condition in t, which the kernels apply themselves.
+struct LinkSet {
+    DevBuf buf[2][LINK_NFMT];  // [output parity][format]
+};
+
 // Tables of one quark mass (the mass enters through L's corner).
 struct TableSet {
     double mq = 0;
@@ -162,7 +170,8 @@ struct dwf_ctx {
                                  // threads may be capturing graphs)
     long V4, V4h, V5h;
     int G64, G32;  // 4D sites per workgroup for FP64 and FP32/FP16 kernels
-    dwf::DevBuf links[2][dwf::LINK_NFMT];  // [output parity][format]
+    std::shared_ptr<dwf::LinkSet> lset;
+    dwf::DevBuf (*links)[dwf::LINK_NFMT] = nullptr;  // lset->buf: [output parity][format]
     std::map<double, std::unique_ptr<dwf::TableSet>> tables;
     std::mutex tables_mtx;  // the table map is shared with the server's threads
     std::mutex mtx;  // one call at a time per context

@@ -863,36 +863,39 @@ int Engine<Real, F, FY, LF>::time_kernels(int launches, double* ms, double* byte
             default: return kD(nullptr);
         }
     };
-    // one event pair around every launch: the average is the kernels' own
-    // device time, without the dispatch gap between back-to-back launches
-    std::vector<hipEvent_t> ev(2 * (size_t)launches, nullptr);
+    // The five kernels run in iteration order (E A B C D), so each finds the
+    // caches as an iteration leaves them; one event pair around every launch,
+    // so the averages are the kernels' own device time.
+    const int nk = 5;
+    std::vector<hipEvent_t> ev(2 * (size_t)launches * nk, nullptr);
     for (auto& e : ev) DWF_HIP(hipEventCreate(&e));
     const double sb = spinor_bytes(prec) * (double)c->V5h * K;
     const double yb = (prec == DWF_PREC_FP64 ? 192.0 : 96.0) * (double)c->V5h * K;
     const double lb = (double)c->V4h * 8.0 * link_bytes(link_fmt);
     const double model[5] = {4 * sb, 2 * sb + lb, 3 * sb + lb, 2 * sb + lb, 4 * sb + 2 * yb + lb};
     int result = DWF_OK;
-    for (int k = 0; k < 5 && result == DWF_OK; ++k) {
-        hipError_t e = runk(k);  // warm-up launch
-        for (int i = 0; i < launches && e == hipSuccess; ++i) {
-            e = hipEventRecord(ev[2 * i], s);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < nk && e == hipSuccess; ++k) e = runk(k);  // warm-up iteration
+    for (int i = 0; i < launches && e == hipSuccess; ++i)
+        for (int k = 0; k < nk && e == hipSuccess; ++k) {
+            const size_t j = 2 * ((size_t)i * nk + k);
+            e = hipEventRecord(ev[j], s);
             if (e == hipSuccess) e = runk(k);
-            if (e == hipSuccess) e = hipEventRecord(ev[2 * i + 1], s);
+            if (e == hipSuccess) e = hipEventRecord(ev[j + 1], s);
         }
-        if (e == hipSuccess) e = hipEventSynchronize(ev[2 * launches - 1]);
+    if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+    for (int k = 0; k < nk && e == hipSuccess; ++k) {
         double tot = 0;
         for (int i = 0; i < launches && e == hipSuccess; ++i) {
+            const size_t j = 2 * ((size_t)i * nk + k);
             float t = 0;
-            e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+            e = hipEventElapsedTime(&t, ev[j], ev[j + 1]);
             tot += t;
-        }
-        if (e != hipSuccess) {
-            result = fail(DWF_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
-            break;
         }
         ms[k] = tot / launches;
         bytes[k] = model[k];
     }
+    if (e != hipSuccess) result = fail(DWF_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
     for (auto& e : ev) (void)hipEventDestroy(e);
     return result;
 }

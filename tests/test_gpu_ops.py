@@ -137,6 +137,21 @@ def test_gamma5_hermiticity_on_gpu(contexts):
     assert abs(a - b) <= 1e-12 * abs(a)
 
 
+def test_contexts_share_one_field():
+    """Contexts on the same gauge field share its resident links (they do not
+    depend on Ns, the masses or the time boundary): the second context keeps
+    working after the first one is destroyed, with its own Ns and boundary."""
+    import paper_1101_0423_amd as dwf
+    P = PROBS["ragged"]
+    a = dwf.Context(P.U, P.dims, 8, 1.8, 0.02, np.zeros(8), np.ones(8), antiperiodic_t=False)
+    b = P.context()
+    a.close()
+    got = b.apply(dwf.OP_D, P.b, prec=0)
+    b.close()
+    exp = oracle_op(P, dwf.OP_D, P.b)
+    assert rel(got, exp) <= TOL[0]
+
+
 def test_full_size_operator_parity():
     """16^3x32, Ns = 16, the configuration of the primary solve: C, C^dag and D
     in FP64 and FP32 against the oracle over the whole lattice."""
