@@ -232,19 +232,27 @@ template <class Real, class F, class LF, bool HOP, int MIXM, class Pro, class Ep
 hipError_t launch_dwf(const Geom& g, const F& in, const LF& links, const Real* table, const Pro& pro,
                       const Epi& epi, KOpt o, hipStream_t st) {
     int T = round_up(g.G * g.Ns, 64);
-    size_t sm = kernel_smem<Real>(g.G, g.Ns, HOP, MIXM != MIX_NONE);
+    // Ns = 16 with a recurrence-form M5 / M5^T: applied in registers, no LDS buffer
+    constexpr bool STRUCT = MIXM == MIX_SA || MIXM == MIX_AS;
+    const bool reg = STRUCT && g.Ns == 16;
+    size_t sm = kernel_smem<Real>(g.G, g.Ns, HOP, MIXM != MIX_NONE && !reg);
     const int rpb = o.rpb > 0 && o.rpb < o.nrhs ? o.rpb : o.nrhs;
     o.rpb = rpb;
     const unsigned ng = o.ngroups > 0 ? (unsigned)o.ngroups : (unsigned)((o.nrhs + rpb - 1) / rpb);
     const dim3 grid((unsigned)g.nblocks * ng), block(T);
     if (g.Ns <= 8)
-        return launch_kernel(k_dwf<Real, F, LF, 8, HOP, MIXM, Pro, Epi>, grid, block, sm, st, g, in, links, table,
-                             pro, epi, o);
-    if (g.Ns <= 16)
-        return launch_kernel(k_dwf<Real, F, LF, 16, HOP, MIXM, Pro, Epi>, grid, block, sm, st, g, in, links, table,
-                             pro, epi, o);
-    return launch_kernel(k_dwf<Real, F, LF, 32, HOP, MIXM, Pro, Epi>, grid, block, sm, st, g, in, links, table, pro,
-                         epi, o);
+        return launch_kernel(k_dwf<Real, F, LF, 8, HOP, MIXM, false, Pro, Epi>, grid, block, sm, st, g, in, links,
+                             table, pro, epi, o);
+    if (g.Ns <= 16) {
+        if constexpr (STRUCT)
+            if (reg)
+                return launch_kernel(k_dwf<Real, F, LF, 16, HOP, MIXM, true, Pro, Epi>, grid, block, sm, st, g, in,
+                                     links, table, pro, epi, o);
+        return launch_kernel(k_dwf<Real, F, LF, 16, HOP, MIXM, false, Pro, Epi>, grid, block, sm, st, g, in, links,
+                             table, pro, epi, o);
+    }
+    return launch_kernel(k_dwf<Real, F, LF, 32, HOP, MIXM, false, Pro, Epi>, grid, block, sm, st, g, in, links,
+                         table, pro, epi, o);
 }
 
 // finish kernel modes

@@ -20,6 +20,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace dwf {
@@ -550,6 +552,96 @@ __device__ __forceinline__ void mix_structured(Real* base, const Real* __restric
 }
 
 // ---------------------------------------------------------------------------
+// M5 and M5^T in registers for Ns = 16.  The 16 slices of a 4D site sit in one
+// 16-lane row of the wavefront (lane = s), so the recurrences above run across
+// lanes with DPP row moves instead of an LDS transpose:
+//   - the sweep al_k = F_k x_k - G_k al_{k-1} is a linear recurrence, done as
+//     a Hillis-Steele scan (shifts by 1, 2, 4, 8 within the row, multiplied by
+//     the products of the -G_j they skip);
+//   - the corner equation needs al_{N-1} and the first input in every lane
+//     (row broadcasts);
+//   - Y and Y^T are one cyclic neighbour each (row rotation).
+// The recurrence runs with s reversed for one chirality (REV): the shifts
+// then go the other way along the row.
+// ---------------------------------------------------------------------------
+
+namespace dpp {
+// DPP controls (row = 16 lanes): lane i reads lane i - n (shr), i + n (shl),
+// (i - n) mod 16 (ror), or lane n of its row (bcast); out-of-row reads give 0.
+constexpr int shr(int n) { return 0x110 + n; }
+constexpr int shl(int n) { return 0x100 + n; }
+constexpr int ror(int n) { return 0x120 + n; }
+constexpr int bcast(int n) { return 0x150 + n; }
+
+template <int CTRL>
+__device__ __forceinline__ float mov(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double mov(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+}  // namespace dpp
+
+// value at recurrence index k - D (0 if k < D)
+template <bool REV, int D, class Real>
+__device__ __forceinline__ Real rshift(Real x) {
+    return dpp::mov<REV ? dpp::shl(D) : dpp::shr(D)>(x);
+}
+// value at recurrence index (k - 1) mod 16
+template <bool REV, class Real>
+__device__ __forceinline__ Real rprev(Real x) {
+    return dpp::mov<REV ? dpp::ror(15) : dpp::ror(1)>(x);
+}
+// value at recurrence index K (0 or 15) of the lane's row
+template <bool REV, int K, class Real>
+__device__ __forceinline__ Real ridx(Real x) {
+    return dpp::mov<dpp::bcast(REV ? 15 - K : K)>(x);
+}
+
+// One chirality block (12 components) of M5 (MODE = MIX_SA) or M5^T / M5^T g5
+// (MIX_AS) on the lane's slice s, coefficients C = [F G B P Q O][16] of that
+// block in recurrence order.  Every lane of the row must execute it.
+template <class Real, int MODE, bool REV>
+__device__ __forceinline__ void mix_reg16(Real* v, const Real* __restrict__ C, int s) {
+    const int k = REV ? 15 - s : s;
+    const Real F = C[k], G = C[16 + k], B = C[32 + k], P = C[48 + k], Q = C[64 + k], O = C[80 + k];
+    const Real F0 = C[0], G0 = C[16];
+    // scan multipliers: A_d(k) = prod_{j = k-d+1..k} (-G_j), zero where k < d
+    const Real A1 = k ? -G : (Real)0;
+    const Real A2 = A1 * rshift<REV, 1>(A1);
+    const Real A4 = A2 * rshift<REV, 2>(A2);
+    const Real A8 = A4 * rshift<REV, 4>(A4);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const Real h = v[c];
+        Real x;  // input of the X solve
+        if constexpr (MODE == MIX_SA)
+            x = h;
+        else
+            x = P * h + Q * rprev<REV>(h);  // Y^T sqrt(w)^-1 h
+        Real al = k ? F * x : (Real)0;
+        al += A1 * rshift<REV, 1>(al);
+        al += A2 * rshift<REV, 2>(al);
+        al += A4 * rshift<REV, 4>(al);
+        al += A8 * rshift<REV, 8>(al);
+        const Real w0 = F0 * ridx<REV, 0>(x) + G0 * ridx<REV, 15>(al);
+        if constexpr (MODE == MIX_SA) {
+            const Real w = al + B * w0;
+            v[c] = P * w + Q * rprev<REV>(w);  // sqrt(w)^-1 Y w
+        } else {
+            v[c] = O * al + B * w0;  // sign sqrt(w) X^-T (...)
+        }
+        // one component at a time: interleaving them only raises register
+        // pressure (and lowers occupancy) in these memory-bound kernels
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // the fused kernel
 //   phase 1: v = hop(in) on every (site, s) lane     [HOP]
 //            v = prologue(site, s)                   [!HOP]
@@ -594,10 +686,11 @@ __host__ __device__ inline size_t kernel_smem(int G, int Ns, bool hop, bool mix)
     return b;
 }
 
-template <class Real, class F, class LF, int NSMAX, bool HOP, int MIXM, class Pro, class Epi>
-__global__ void __launch_bounds__(256)
+template <class Real, class F, class LF, int NSMAX, bool HOP, int MIXM, bool REGMIX, class Pro, class Epi>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<F, FS>::value ? 4 : 1)))
 k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, KOpt o) {
-    constexpr bool MIX = MIXM != MIX_NONE;
+    // REGMIX: Ns == 16, M5 / M5^T applied in registers (no LDS transpose)
+    constexpr bool MIX = MIXM != MIX_NONE && !REGMIX;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int LS = LdsLink<Real>::STR;
     const int Ns = g.Ns;
@@ -670,6 +763,9 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
                 hop_site<Real>(in, rhs, s, Ns, nb, lk + sl * LdsLink<Real>::SITE, v);
             else
                 pro(rhs, i5, s, v);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 24; ++k) v[k] = 0;
         }
         if constexpr (MIX) {
             if (act) {
@@ -706,6 +802,16 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
 #pragma unroll
                 for (int k = 0; k < 24; ++k) v[k] = src[k];
             }
+        }
+        if constexpr (REGMIX) {
+            // every lane of a row takes part (rows of inactive sites are whole
+            // rows); the coefficient loads stay after the hop, whose register
+            // peak they would otherwise raise
+            __builtin_amdgcn_sched_barrier(0);
+            const Real* tb = table + rhs * o.table_rstride;
+            constexpr bool rev0 = MIXM == MIX_AS, rev1 = MIXM != MIX_AS;  // M5: L_- reversed; M5^T: L_+^T
+            mix_reg16<Real, MIXM, rev0>(v, tb, s);
+            mix_reg16<Real, MIXM, rev1>(v + 12, tb + 6 * 16, s);
         }
         double part = 0;
         if (act) part = epi(rhs, i5, s, v);
