@@ -44,6 +44,18 @@ struct FD {  // FP64 storage and arithmetic
     __device__ __forceinline__ const double2* at(int rhs, long i, int s) const {
         return p + rhs * rstride + 12 * i - 11 * (long)s;
     }
+    template <class R>
+    __device__ __forceinline__ void sload(int rhs, long i, int s, R* v) const {
+        load(rhs, i, s, v);
+    }
+    template <class R>
+    __device__ __forceinline__ void sstore(int rhs, long i, int s, const R* v) const {
+        store(rhs, i, s, v);
+    }
+    template <class R>
+    __device__ __forceinline__ void gather(int rhs, long i, int s, R* v) const {
+        load(rhs, i, s, v);
+    }
     __device__ __forceinline__ void load(int rhs, long i, int s, double* v) const {
         const double2* q = at(rhs, i, s);
 #pragma unroll
@@ -80,6 +92,7 @@ struct FS {  // FP32 storage
     __device__ __forceinline__ const float4* at(int rhs, long i, int s) const {
         return p + rhs * rstride + 6 * i - 5 * (long)s;
     }
+    // cached loads and stores (hop neighbours, data the next kernel gathers)
     __device__ __forceinline__ void load(int rhs, long i, int s, float* v) const {
         const float4* q = at(rhs, i, s);
 #pragma unroll
@@ -91,10 +104,32 @@ struct FS {  // FP32 storage
             v[4 * j + 3] = a.w;
         }
     }
+    __device__ __forceinline__ void gather(int rhs, long i, int s, float* v) const { load(rhs, i, s, v); }
     __device__ __forceinline__ void store(int rhs, long i, int s, const float* v) const {
         float4* q = const_cast<float4*>(at(rhs, i, s));
 #pragma unroll
         for (int j = 0; j < 6; ++j) q[j * ns] = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+    }
+    // streaming (non-temporal) loads and stores: vectors a kernel reads or
+    // writes once, kept from displacing the neighbour data the hop re-reads
+    __device__ __forceinline__ void sload(int rhs, long i, int s, float* v) const {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4* q = (const f4*)at(rhs, i, s);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            f4 a = __builtin_nontemporal_load(q + j * ns);
+            v[4 * j] = a.x;
+            v[4 * j + 1] = a.y;
+            v[4 * j + 2] = a.z;
+            v[4 * j + 3] = a.w;
+        }
+    }
+    __device__ __forceinline__ void sstore(int rhs, long i, int s, const float* v) const {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        f4* q = (f4*)const_cast<float4*>(at(rhs, i, s));
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            __builtin_nontemporal_store(f4{v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]}, q + j * ns);
     }
     __device__ __forceinline__ void load(int rhs, long i, int s, double* v) const {
         float t[24];
@@ -122,32 +157,54 @@ struct FH {  // binary16 storage with one FP32 scale per 5D site; FP32 arithmeti
     __device__ __forceinline__ const uint4* at(int rhs, long i, int s) const {
         return p + rhs * rstride + 3 * i - 2 * (long)s;
     }
+    template <class R>
+    __device__ __forceinline__ void gather(int rhs, long i, int s, R* v) const {
+        load(rhs, i, s, v);
+    }
+    // NT: non-temporal (streaming) access, as for FS
+    template <bool NT = false>
     __device__ __forceinline__ void load(int rhs, long i, int s, float* v) const {
-        const uint4* q = at(rhs, i, s);
-        float n = nrm[rhs * nrstride + i];
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+        const u4* q = (const u4*)at(rhs, i, s);
+        const float* np = nrm + rhs * nrstride + i;
+        const float n = NT ? __builtin_nontemporal_load(np) : *np;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            uint4 a = q[j * ns];
+            const u4 a = NT ? __builtin_nontemporal_load(q + j * ns) : q[j * ns];
             half8_t h = __builtin_bit_cast(half8_t, a);
 #pragma unroll
             for (int k = 0; k < 8; ++k) v[8 * j + k] = (float)h[k] * n;
         }
     }
+    template <bool NT = false>
     __device__ __forceinline__ void store(int rhs, long i, int s, const float* v) const {
+        typedef unsigned int u4 __attribute__((ext_vector_type(4)));
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 24; ++k) m = fmaxf(m, fabsf(v[k]));
         float inv = m > 0.f ? 1.f / m : 0.f;
-        uint4* q = const_cast<uint4*>(at(rhs, i, s));
+        u4* q = (u4*)const_cast<uint4*>(at(rhs, i, s));
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             half8_t h;
 #pragma unroll
             for (int k = 0; k < 8; ++k) h[k] = (_Float16)(v[8 * j + k] * inv);
-            q[j * ns] = __builtin_bit_cast(uint4, h);
+            if (NT)
+                __builtin_nontemporal_store(__builtin_bit_cast(u4, h), q + j * ns);
+            else
+                q[j * ns] = __builtin_bit_cast(u4, h);
         }
-        nrm[rhs * nrstride + i] = m;
+        if (NT)
+            __builtin_nontemporal_store(m, nrm + rhs * nrstride + i);
+        else
+            nrm[rhs * nrstride + i] = m;
     }
+    __device__ __forceinline__ void sload(int rhs, long i, int s, float* v) const { load<true>(rhs, i, s, v); }
+    __device__ __forceinline__ void sstore(int rhs, long i, int s, const float* v) const {
+        store<true>(rhs, i, s, v);
+    }
+    __device__ __forceinline__ void sload(int rhs, long i, int s, double* v) const { load(rhs, i, s, v); }
+    __device__ __forceinline__ void sstore(int rhs, long i, int s, const double* v) const { store(rhs, i, s, v); }
     __device__ __forceinline__ void load(int rhs, long i, int s, double* v) const {
         float t[24];
         load(rhs, i, s, t);
@@ -413,7 +470,7 @@ __device__ __forceinline__ void hop_site(const F& in, int rhs, int s, int Ns, co
     Real pa[24];
 #define DWF_STEP(MU, SIG, L)                                                   \
     {                                                                          \
-        in.load(rhs, (long)nb[L] * Ns + s, s, pa);                             \
+        in.gather(rhs, (long)nb[L] * Ns + s, s, pa);                           \
         _Pragma("unroll") for (int k = 0; k < 18; ++k) U[k] = lk[(L) * LS + k]; \
         hop_dir<MU, SIG>(pa, U, acc);                                          \
     }
@@ -866,14 +923,14 @@ struct ProCgE {
     const double* ecr;
     template <class Real>
     __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const {
-        r.load(rhs, i, s, v);
+        r.sload(rhs, i, s, v);
         const Real a = ecr ? (Real)ecr[rhs] : (Real)1;
         const Real b = (Real)beta[rhs];
         Real q[24];
-        p.load(rhs, i, s, q);
+        p.sload(rhs, i, s, q);
 #pragma unroll
         for (int k = 0; k < 24; ++k) v[k] = a * v[k] + b * q[k];
-        p.store(rhs, i, s, v);
+        p.sstore(rhs, i, s, v);
     }
 };
 
@@ -895,7 +952,7 @@ struct EpiStore {
     F out;
     template <class Real>
     __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
-        out.store(rhs, i, s, v);
+        out.store(rhs, i, s, v);  // the next kernel gathers it: cached
         return RED ? norm2_24(v) : 0.0;
     }
 };
@@ -938,10 +995,10 @@ struct EpiCgB {
     template <class Real>
     __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         Real w[24];
-        p.load(rhs, i, s, w);
+        p.sload(rhs, i, s, w);
 #pragma unroll
         for (int k = 0; k < 24; ++k) w[k] = k < 12 ? w[k] - v[k] : w[k] + v[k];
-        u.store(rhs, i, s, w);
+        u.store(rhs, i, s, w);  // gathered by the next kernel: cached
         return norm2_24(w);
     }
 };
@@ -958,16 +1015,16 @@ struct EpiCgD {
     __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         const Real a = (Real)alpha[rhs];
         Real uu[24], w[24];
-        u.load(rhs, i, s, uu);
-        r.load(rhs, i, s, w);
+        u.sload(rhs, i, s, uu);
+        r.sload(rhs, i, s, w);
 #pragma unroll
         for (int k = 0; k < 24; ++k) w[k] -= a * (uu[k] - v[k]);
-        r.store(rhs, i, s, w);
+        r.sstore(rhs, i, s, w);
         Real yy[24];
-        y.load(rhs, i, s, yy);
+        y.sload(rhs, i, s, yy);
 #pragma unroll
         for (int k = 0; k < 24; ++k) yy[k] += a * uu[k];
-        y.store(rhs, i, s, yy);
+        y.sstore(rhs, i, s, yy);
         return norm2_24(w);
     }
 };
