@@ -112,6 +112,14 @@ dwf::Geom dwf_ctx::geom(int out_parity, bool fp64) const {
     g.antiper = opts.antiperiodic_t ? 1 : 0;
     g.nblocks = (int)((V4h + g.G - 1) / g.G);
     g.xcd = opts.xcd_remap < 0 ? 0 : 1;
+    // t-fastest workgroup order when blocks tile the t-slices exactly
+    const long V3h = V4h / dims[3];
+    g.nsb = 0;
+    g.tchunk = 0;
+    if (g.xcd && V3h % g.G == 0) {
+        g.nsb = (int)(V3h / g.G);
+        g.tchunk = dims[3] % 8 == 0 ? dims[3] / 8 : dims[3];
+    }
     return g;
 }
 

@@ -349,6 +349,8 @@ struct Geom {
     int antiper;   // 1: links crossing the t boundary carry a factor -1
     int nblocks;
     int xcd;       // 1: map consecutive lattice blocks onto one XCD
+    int nsb;       // > 0: workgroups go t-fastest: blocks per t-slice (V3h / G) ...
+    int tchunk;    // ... in chunks of tchunk t-slices (one chunk per XCD)
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
@@ -361,6 +363,19 @@ __device__ __forceinline__ int xcd_remap(int b, int nb, int on) {
     int q = nb / NX, r = nb - q * NX;
     int x = b % NX, idx = b / NX;
     return x < r ? x * (q + 1) + idx : r * (q + 1) + (x - r) * q + idx;
+}
+
+// Lattice block of a workgroup's position L in the (XCD-remapped) order.  With
+// g.nsb > 0 the order runs t-fastest through every chunk of tchunk t-slices:
+// L = (chunk, spatial block, t in chunk), so the +-t neighbours of a block
+// were read one workgroup earlier and the +-z ones a few spatial blocks
+// earlier, both still in the XCD's L2.  A bijection on [0, nblocks).
+__device__ __forceinline__ int block_of(int L, const Geom& g) {
+    if (g.nsb <= 0) return L;
+    const int per = g.nsb * g.tchunk;
+    const int chunk = L / per, rem = L - chunk * per;
+    const int sb = rem / g.tchunk, tt = rem - sb * g.tchunk;
+    return (chunk * g.tchunk + tt) * g.nsb + sb;
 }
 
 // ---------------------------------------------------------------------------
@@ -756,7 +771,7 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
     // workgroup -> (group of right-hand sides, lattice block)
     const int L = xcd_remap(blockIdx.x, gridDim.x, g.xcd);
     const int grp = L / g.nblocks;
-    const int lb = L - grp * g.nblocks;
+    const int lb = block_of(L - grp * g.nblocks, g);
     const int rpb = o.rpb > 0 ? o.rpb : o.nrhs;
     const int nsel = o.glist ? o.glist[0] : o.nrhs;
     const int j0 = grp * rpb, j1 = min(nsel, j0 + rpb);
