@@ -100,7 +100,15 @@ typedef struct dwf_solve_params {
     int use_guess;           /* 1: x holds an initial guess on entry; 0: start from zero  */
     int debug_stall_after;   /* test hook: >0 declares reliable updates stalled after this
                                 many restarts, forcing the defect-correction fallback     */
+    int system;              /* DWF_SYSTEM_D (default): D x = b of Eq. (5), full 5D lattice;
+                                DWF_SYSTEM_CCDAG: C C^dag w = b on the odd sites (the solve
+                                of the HMC force, Sec. 2.1): the even sites of b are
+                                ignored and those of w are zero; true_residual is then
+                                ||b_o - C C^dag w|| / ||b_o||                               */
 } dwf_solve_params;
+
+#define DWF_SYSTEM_D 0
+#define DWF_SYSTEM_CCDAG 1
 
 typedef struct dwf_solve_stats {
     int status;              /* DWF_OK or DWF_ENOCONV                                     */

@@ -62,6 +62,8 @@ def lib():
             f.argtypes = opargs
         L.orc_solve.argtypes = opargs + [ctypes.c_double, ctypes.c_int, _ip, _dp]
         L.orc_solve.restype = ctypes.c_int
+        L.orc_solve_ccdag.argtypes = opargs + [ctypes.c_double, ctypes.c_int, _ip, _dp]
+        L.orc_solve_ccdag.restype = ctypes.c_int
         L.orc_cgne_full.argtypes = opargs + [ctypes.c_double, ctypes.c_int, _ip, _dp]
         L.orc_cgne_full.restype = ctypes.c_int
         L.orc_true_residual.argtypes = opargs
@@ -186,6 +188,20 @@ def solve(U, dims, ns, m0, mq, sigma, omega, b, tol=1e-12, maxiter=100000, x0=No
     if rc < 0:
         raise ValueError("singular fifth-dimension matrix")
     return x, dict(converged=(rc == 0), iters=it.value, schur_res=res.value)
+
+
+def solve_ccdag(U, dims, ns, m0, mq, sigma, omega, b, tol=1e-12, maxiter=100000, w0=None, bct=1.0):
+    """C C^dag w = b on the odd sites by Algorithm 1 (even sites of b ignored,
+    of w zero).  Returns (w, info dict)."""
+    U, b = _f64(U), _f64(b)
+    w = np.zeros_like(b) if w0 is None else _f64(w0).copy()
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0)
+    rc = lib().orc_solve_ccdag(_p(U), _dims(dims), ns, m0, mq, _p(_f64(sigma)), _p(_f64(omega)), bct,
+                               _p(b), _p(w), tol, maxiter, ctypes.byref(it), ctypes.byref(res))
+    if rc < 0:
+        raise ValueError("singular fifth-dimension matrix")
+    return w, dict(converged=(rc == 0), iters=it.value, relres=res.value)
 
 
 def cgne_full(U, dims, ns, m0, mq, sigma, omega, b, tol=1e-12, maxiter=100000, bct=1.0):

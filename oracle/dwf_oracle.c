@@ -47,6 +47,10 @@ typedef double complex cplx;
 /* Gamma matrices (chiral basis).                                            */
 /* ------------------------------------------------------------------------ */
 
+/* Loops over fewer 5D sites than this run on one thread: on small lattices the
+ * cost of waking a thread team exceeds the work (the arithmetic is the same). */
+#define OMP_MIN_WORK 16384
+
 static cplx G[5][4][4];
 static int g_ready = 0;
 
@@ -140,7 +144,7 @@ static void hop_apply(const lat_t *l, int Ns, const cplx *U, double bct,
                       int only_parity, const cplx *in, cplx *out)
 {
     gamma_init();
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (l->V * Ns > OMP_MIN_WORK)
     for (long n = 0; n < l->V; n++) {
         int c[4];
         coords(l, n, c);
@@ -369,7 +373,7 @@ static void apply_s(const lat_t *l, int Ns, const double *Mp, const double *Mm,
             Pp[i][j] = 0.5 * ((i == j) + G[4][i][j]);   /* P_+ = (1 + gamma_5)/2 */
             Pm[i][j] = 0.5 * ((i == j) - G[4][i][j]);   /* P_- = (1 - gamma_5)/2 */
         }
-#pragma omp parallel
+#pragma omp parallel if (l->V * Ns > OMP_MIN_WORK)
     {
         cplx *pp = malloc(sizeof(cplx) * Ns * 12), *pm = malloc(sizeof(cplx) * Ns * 12);
 #pragma omp for schedule(static)
@@ -423,7 +427,7 @@ void orc_L(const int *dims, int Ns, double m0, double mq, const double *in, doub
 static void g5_apply(long nsites5, const cplx *in, cplx *out)
 {
     gamma_init();
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nsites5 > OMP_MIN_WORK)
     for (long n = 0; n < nsites5; n++) {
         cplx t[12];
         for (int i = 0; i < 4; i++)
@@ -593,7 +597,7 @@ void orc_schur_cdag(const double *U, const int *dims, int Ns, double m0, double 
 static double norm2(long N, const cplx *a)
 {
     double s = 0;
-#pragma omp parallel for reduction(+ : s)
+#pragma omp parallel for reduction(+ : s) if (N > 4 * OMP_MIN_WORK)
     for (long i = 0; i < N; i++) s += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
     return s;
 }
@@ -721,6 +725,65 @@ done:
     free(Yip); free(Yim); free(S2p); free(S2m); free(S2ip); free(S2im);
     schur_free(&S);
     return rc;
+}
+
+/*
+ * The solve the hybrid Monte Carlo force needs: C C^dag w = b on the odd sites
+ * (the paper's use of CG on C C^dag, Sec. 2.1), by Algorithm 1 as printed with
+ * A = C C^dag applied as C (C^dag p):
+ *   r = b - A w;  p = r;  alpha = |r|^2 / (p, A p);  w += alpha p;
+ *   r -= alpha A p;  beta = |r_new|^2 / |r|^2;  p = r + beta p,
+ * stopping when |r| <= tol |b|.  The even sites of b are ignored and the even
+ * sites of w are zero.  w holds the initial guess on entry.
+ * Returns 0 if converged, 1 if maxiter was reached, -1 on a singular
+ * fifth-dimension matrix.
+ */
+int orc_solve_ccdag(const double *U, const int *dims, int Ns, double m0, double mq,
+                    const double *sigma, const double *omega, double bct,
+                    const double *b, double *w, double tol, int maxiter,
+                    int *iters, double *relres)
+{
+    schur_t S;
+    if (schur_init(&S, U, dims, Ns, m0, mq, sigma, omega, bct)) { schur_free(&S); return -1; }
+    long N = S.N, V = S.l.V;
+    cplx *bo = malloc(sizeof(cplx) * N), *r = malloc(sizeof(cplx) * N), *p = malloc(sizeof(cplx) * N);
+    cplx *t = malloc(sizeof(cplx) * N), *ap = malloc(sizeof(cplx) * N);
+    cplx *ww = (cplx *)w;
+    const cplx *bb = (const cplx *)b;
+    for (long n = 0; n < V; n++) {
+        int c[4];
+        coords(&S.l, n, c);
+        int odd = parity(c);
+        for (long k = n * Ns * 12; k < (n + 1) * Ns * 12; k++) {
+            bo[k] = odd ? bb[k] : 0;
+            if (!odd) ww[k] = 0;
+        }
+    }
+    /* r = b - C C^dag w */
+    schur_cdag(&S, ww, t);
+    schur_c(&S, t, ap);
+    for (long i = 0; i < N; i++) { r[i] = bo[i] - ap[i]; p[i] = r[i]; }
+    double bn = norm2(N, bo), rr = norm2(N, r);
+    int k = 0;
+    while (rr > tol * tol * bn && k < maxiter) {
+        schur_cdag(&S, p, t);
+        schur_c(&S, t, ap);
+        double pap = 0;
+        for (long i = 0; i < N; i++) pap += creal(conj(p[i]) * ap[i]);
+        if (!(pap > 0)) break;
+        double alpha = rr / pap;
+        for (long i = 0; i < N; i++) { ww[i] += alpha * p[i]; r[i] -= alpha * ap[i]; }
+        double rr_new = norm2(N, r);
+        double beta = rr_new / rr;
+        for (long i = 0; i < N; i++) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+        k++;
+    }
+    *iters = k;
+    *relres = bn > 0 ? sqrt(rr / bn) : 0;
+    free(bo); free(r); free(p); free(t); free(ap);
+    schur_free(&S);
+    return (rr <= tol * tol * bn) ? 0 : 1;
 }
 
 /* CG on the normal equations of the unpreconditioned 5D operator (no even-odd

@@ -7,6 +7,7 @@ Importing the package loads the library and raises if it has not been built.
 from .binding import (  # noqa: F401
     DWF_EBUSY, DWF_EDEVICE, DWF_EINVAL, DWF_ENOCONV, DWF_ENOMEM, DWF_ENOTFOUND, DWF_OK, DWF_PENDING,
     OP_C, OP_CCDAG, OP_CDAG, OP_D, OP_DDAG, OP_DW, OP_HOP_EO, OP_HOP_OE, OP_M5, OP_M5T,
-    PREC_FP16, PREC_FP32, PREC_FP64, Context, DwfError, SolveParams, SolveStats, ServerStats,
+    PREC_FP16, PREC_FP32, PREC_FP64, SYSTEM_CCDAG, SYSTEM_D, Context, DwfError, SolveParams, SolveStats,
+    ServerStats,
     default_params, lib, lib_path, poll, server_stats, EXPORTED,
 )

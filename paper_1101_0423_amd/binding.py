@@ -27,6 +27,10 @@ EXPORTED = [
 ]
 
 
+SYSTEM_D = 0
+SYSTEM_CCDAG = 1
+
+
 class DwfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libdwf error {code}: {msg}")
@@ -42,7 +46,7 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_prec", ctypes.c_int), ("reliable", ctypes.c_int),
                 ("eps_inner", ctypes.c_double), ("maxiter", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("link_compress", ctypes.c_int), ("use_guess", ctypes.c_int),
-                ("debug_stall_after", ctypes.c_int)]
+                ("debug_stall_after", ctypes.c_int), ("system", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):

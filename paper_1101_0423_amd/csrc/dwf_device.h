@@ -1018,7 +1018,10 @@ struct EpiCgB {
     }
 };
 
-// CG kernel D: q = u - v (v = M5 D^OE t3), y += alpha u, r -= alpha q; returns |r|^2.
+// CG kernel D: q = u - v (v = M5 D^OE t3), r -= alpha q; returns |r|^2.  The
+// solution takes y += alpha u (D x = b: y = C^dag w is tracked, so r is the
+// residual of C y = b''), or w += alpha p for the right-hand sides with
+// accp[rhs] set (C C^dag w = b: Algorithm 1 on A = C C^dag as printed).
 template <class FU, class FR, class FY>
 struct EpiCgD {
     static constexpr bool kReduce = true;
@@ -1026,6 +1029,8 @@ struct EpiCgD {
     FR r;
     FY y;
     const double* alpha;
+    FU p;
+    const int* accp;
     template <class Real>
     __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         const Real a = (Real)alpha[rhs];
@@ -1035,6 +1040,7 @@ struct EpiCgD {
 #pragma unroll
         for (int k = 0; k < 24; ++k) w[k] -= a * (uu[k] - v[k]);
         r.sstore(rhs, i, s, w);
+        if (accp && accp[rhs]) p.sload(rhs, i, s, uu);
         Real yy[24];
         y.sload(rhs, i, s, yy);
 #pragma unroll

@@ -370,6 +370,7 @@ int dwf_submit_mass(dwf_ctx* c, const double* b, double mq, const dwf_solve_para
     if (p.inner_prec < DWF_PREC_FP64 || p.inner_prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "bad inner_prec");
     if (p.maxiter < 1) return fail(DWF_EINVAL, "maxiter must be >= 1");
     if (p.link_compress < -1 || p.link_compress > 1) return fail(DWF_EINVAL, "link_compress must be -1, 0 or 1");
+    if (p.system != DWF_SYSTEM_D && p.system != DWF_SYSTEM_CCDAG) return fail(DWF_EINVAL, "unknown system");
     p.use_guess = 0;
     DWF_HIP(hipSetDevice(c->device));
     int rc;

@@ -72,7 +72,8 @@ namespace {
 enum { B_E = 0, B_O, BP_E, BP_O, BPP, YH_E, YH_O, T64_E, NF64 };
 enum { L_R = NF64, L_P, L_U, L_T1, L_T23, L_Y, NFALL };
 // per-slot masks on the device (each has its own pinned staging row)
-enum { M_SETUP = 0, M_GUESS, M_NOGUESS, M_OUTER, M_REVERT, M_RESET, M_RUFIN, M_POST, M_FINAL, M_AGAIN, NMASK };
+enum { M_SETUP = 0, M_GUESS, M_NOGUESS, M_OUTER, M_REVERT, M_RESET, M_RUFIN, M_POST, M_FINAL, M_AGAIN,
+       M_SETUP0, M_SETUP1, M_GUESS1, M_F0, M_F1, M_FIN0, M_FORM, NMASK };
 enum { LIST_INNER = 0, LIST_RUFIN, NLIST };
 
 constexpr int kItersPerGraph = 4;
@@ -88,6 +89,7 @@ struct SlotCtl {
     dwf_solve_params p{};
     double mq = 0;
     int use_guess = 0;
+    int form = DWF_SYSTEM_D;  // D x = b, or C C^dag w = b on the odd sites
     int mode_ru = 1, cycles = 0, fellback = 0, noprog = 0, ru_restarts = 0, have_backup = 0, reverted = 0;
     int failed = 0, round = 0, restarts = 0, stuck = 0;
     double rhat_prev = 0, tol_schur = 0, true_res = 0, schur_res = 0, bnorm2 = 0, bpp2 = 0;
@@ -185,6 +187,7 @@ class Engine : public EngineBase {
         q.p = p;
         q.mq = mq;
         q.use_guess = x0_dev != nullptr;
+        q.form = p.system == DWF_SYSTEM_CCDAG ? DWF_SYSTEM_CCDAG : DWF_SYSTEM_D;
         q.mode_ru = p.reliable ? 1 : 0;
         q.tol_schur = p.tol;
         q.eps_dc = p.eps_inner > 0 ? p.eps_inner
@@ -216,7 +219,12 @@ class Engine : public EngineBase {
     int retire(int r, double* x_dev, SlotResult* res) override {
         if (r < 0 || r >= K || sl[r].phase != PH_DONE) return fail(DWF_EINVAL, "slot not done");
         SlotCtl& q = sl[r];
-        if (x_dev) DWF_HIP(half_to_host(c, w.f(BP_E), w.f(BP_O), 1, x_dev, s, r));
+        if (x_dev) {
+            if (q.form == DWF_SYSTEM_CCDAG)  // w on the odd sites, zero even half (B_E)
+                DWF_HIP(half_to_host(c, w.f(B_E), w.f(YH_O), 1, x_dev, s, r));
+            else
+                DWF_HIP(half_to_host(c, w.f(BP_E), w.f(BP_O), 1, x_dev, s, r));
+        }
         if (res) {
             const double V = (double)c->V5h;
             const double fo = V * (2640.0 + 96.0 * c->Ns + 72.0);
@@ -230,7 +238,9 @@ class Engine : public EngineBase {
             res->true_residual = q.true_res;
             res->schur_residual = q.schur_res;
             res->seconds = q.seconds;
-            res->flops = flops_per_iter(c) * res->iters + fo * q.restarts + fsetup + ffinal * (q.round + 1);
+            res->flops = flops_per_iter(c) * res->iters +
+                         (q.form == DWF_SYSTEM_CCDAG ? 2.0 * fo * q.restarts
+                                                     : fo * q.restarts + fsetup + ffinal * (q.round + 1));
             res->bytes = bytes_per_iter(c, prec, link_fmt) * res->iters + 12.0 * V * 192.0 * (q.restarts + 4);
         }
         q.phase = PH_FREE;
@@ -438,16 +448,50 @@ class Engine : public EngineBase {
             g64(par), d(in), lk64[par], s64(ST_M5), ProLoad<FD>{d(in)},
             EpiLin<FD, FD, false, false>{d(a), d(out), 1.0, -1.0}, kopt(m, false), s);
     }
-    // rhat = b'' - C yhat_o (FP64), r_lo = rhat, y_lo = 0, rr = aux = |rhat|^2
-    hipError_t outer_residual(const int* m) {
-        hipError_t e = launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiStore<FD>>(
-            g64(0), d(YH_O), lk64[0], s64(ST_M5), ProLoad<FD>{d(YH_O)}, EpiStore<FD>{d(T64_E)}, kopt(m, false), s);
+    // rhat = b'' - C yhat_o (FP64), r_lo = rhat, y_lo = 0, rr = aux = |rhat|^2.
+    // For C C^dag w = b (form 1) yhat_o is w and C^dag w is formed first (in
+    // BP_O, with T64_E as the even temporary), so that rhat = b - C C^dag w.
+    hipError_t outer_residual(const int* m, int form) {
+        hipError_t e = hipSuccess;
+        int yh = YH_O;
+        if (form == DWF_SYSTEM_CCDAG) {
+            e = launch_dwf<double, FD, LinkD18, false, MIX_AS, ProLoad<FD>, EpiStore<FD>>(
+                g64(1), d(YH_O), lk64[1], s64(ST_M5TG5), ProLoad<FD>{d(YH_O)}, EpiStore<FD>{d(BP_O)}, kopt(m, false),
+                s);  // M5^T g5 w
+            if (e == hipSuccess)
+                e = launch_dwf<double, FD, LinkD18, true, MIX_AS, ProLoad<FD>, EpiStore<FD>>(
+                    g64(0), d(BP_O), lk64[0], s64(ST_M5T), ProLoad<FD>{d(BP_O)}, EpiStore<FD>{d(T64_E)},
+                    kopt(m, false), s);  // M5^T D^EO (...)
+            if (e == hipSuccess)
+                e = launch_dwf<double, FD, LinkD18, true, MIX_NONE, ProLoad<FD>, EpiLin<FD, FD, false, true>>(
+                    g64(1), d(T64_E), lk64[1], nullptr, ProLoad<FD>{d(T64_E)},
+                    EpiLin<FD, FD, false, true>{d(YH_O), d(BP_O), 1.0, -1.0}, kopt(m, false), s);  // C^dag w
+            if (e != hipSuccess) return e;
+            yh = BP_O;
+        }
+        e = launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiStore<FD>>(
+            g64(0), d(yh), lk64[0], s64(ST_M5), ProLoad<FD>{d(yh)}, EpiStore<FD>{d(T64_E)}, kopt(m, false), s);
         if (e != hipSuccess) return e;
         e = launch_dwf<double, FD, LinkD18, true, MIX_SA, ProLoad<FD>, EpiOuter<FD, FD, F, FY>>(
             g64(1), d(T64_E), lk64[1], s64(ST_M5), ProLoad<FD>{d(T64_E)},
-            EpiOuter<FD, FD, F, FY>{d(BPP), d(YH_O), lo(L_R), ylo()}, kopt(m, true), s);
+            EpiOuter<FD, FD, F, FY>{d(BPP), d(yh), lo(L_R), ylo()}, kopt(m, true), s);
         if (e != hipSuccess) return e;
         return fin(g64(1).nblocks, FIN_OUTER, m);
+    }
+    // the outer residual of the slots in host mask mk, each with its form
+    int outer_residual_masked(int mk) {
+        const int n0 = upload_mask(M_F0, [&](int r) { return hmask[mk][r] && sl[r].form == DWF_SYSTEM_D; });
+        const int n1 = upload_mask(M_F1, [&](int r) { return hmask[mk][r] && sl[r].form == DWF_SYSTEM_CCDAG; });
+        if (upload_err != hipSuccess) {
+            hipError_t e = upload_err;
+            upload_err = hipSuccess;
+            return fail(DWF_EDEVICE, std::string("slot mask upload: ") + hipGetErrorString(e));
+        }
+        hipError_t e = hipSuccess;
+        if (n0) e = outer_residual(dmask[M_F0], DWF_SYSTEM_D);
+        if (n1 && e == hipSuccess) e = outer_residual(dmask[M_F1], DWF_SYSTEM_CCDAG);
+        if (e != hipSuccess) return fail(DWF_EDEVICE, std::string("outer residual: ") + hipGetErrorString(e));
+        return DWF_OK;
     }
     // res = b - D x on one parity, |res|^2 into the block sums; yx = (Y x) of
     // the other parity, xx = X x of this one
@@ -478,7 +522,7 @@ class Engine : public EngineBase {
     hipError_t kD(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiCgD<F, F, FY>>(
             glo(1), lo(L_T23), lk[1], slo(ST_M5), ProLoad<F>{lo(L_T23)},
-            EpiCgD<F, F, FY>{lo(L_U), lo(L_R), ylo(), w.st.alpha}, kopt_in(live, true), s);
+            EpiCgD<F, F, FY>{lo(L_U), lo(L_R), ylo(), w.st.alpha, lo(L_P), dmask[M_FORM]}, kopt_in(live, true), s);
     }
     hipError_t iteration() {
         hipError_t e;
@@ -544,31 +588,47 @@ class Engine : public EngineBase {
     int setup() {
         int* m = dmask[M_SETUP];
         upload_mask(M_SETUP, [&](int r) { return sl[r].phase == PH_SETUP; });
+        const int n0 = upload_mask(M_SETUP0, [&](int r) { return hmask[M_SETUP][r] && sl[r].form == DWF_SYSTEM_D; });
+        const int n1 =
+            upload_mask(M_SETUP1, [&](int r) { return hmask[M_SETUP][r] && sl[r].form == DWF_SYSTEM_CCDAG; });
+        // the per-slot form flag that kernel D reads
+        upload_mask(M_FORM, [&](int r) {
+            return (hmask[M_SETUP][r] ? sl[r].form : (sl[r].phase == PH_FREE ? 0 : sl[r].form)) == DWF_SYSTEM_CCDAG;
+        });
         CKU();
         CKE(norm64(0, B_E, m));
         CKE(fin(g64(0).nblocks, FIN_AUX, m));
         CKR(pull());
         for (int r = 0; r < K; ++r)
-            if (hmask[M_SETUP][r]) sl[r].bnorm2 = h_aux(r);
+            if (hmask[M_SETUP][r]) sl[r].bnorm2 = sl[r].form == DWF_SYSTEM_D ? h_aux(r) : 0.0;  // even part of b
         CKE(norm64(1, B_O, m));
         CKE(fin(g64(1).nblocks, FIN_AUX, m));
         CKR(pull());
         for (int r = 0; r < K; ++r)
             if (hmask[M_SETUP][r]) sl[r].bnorm2 += h_aux(r);
-        int ng = upload_mask(M_GUESS, [&](int r) { return hmask[M_SETUP][r] && sl[r].use_guess; });
-        CKU();
-        int nz = upload_mask(M_NOGUESS, [&](int r) { return hmask[M_SETUP][r] && !sl[r].use_guess; });
+        // initial yhat_o: (S2^-1 x0)_o for D x = b, the odd part of w0 for C C^dag w = b, else 0
+        const int ng = upload_mask(M_GUESS, [&](int r) { return hmask[M_SETUP0][r] && sl[r].use_guess; });
+        const int ng1 = upload_mask(M_GUESS1, [&](int r) { return hmask[M_SETUP1][r] && sl[r].use_guess; });
+        const int nz = upload_mask(M_NOGUESS, [&](int r) { return hmask[M_SETUP][r] && !sl[r].use_guess; });
         CKU();
         if (ng) CKE(local64(1, BP_O, TB_S2INV, YH_O, dmask[M_GUESS]));
+        if (ng1) CKE(half_copy(c, w.f(YH_O), w.f(BP_O), K, dmask[M_GUESS1], s));
         if (nz) CKE(half_zero(c, w.f(YH_O), K, s, dmask[M_NOGUESS]));
-        CKE(local64(0, B_E, TB_S1, BP_E, m));
-        CKE(local64(1, B_O, TB_S1, BP_O, m));
-        CKE(xmy_m5hop64(1, BP_E, BP_O, BPP, true, m));
-        CKE(fin(g64(1).nblocks, FIN_AUX, m));
+        if (n1) {
+            // C C^dag w = b: b'' is the odd part of b; B_E becomes the zero even half of w
+            CKE(half_copy(c, w.f(BPP), w.f(B_O), K, dmask[M_SETUP1], s));
+            CKE(half_zero(c, w.f(B_E), K, s, dmask[M_SETUP1]));
+        }
+        if (n0) {
+            CKE(local64(0, B_E, TB_S1, BP_E, dmask[M_SETUP0]));
+            CKE(local64(1, B_O, TB_S1, BP_O, dmask[M_SETUP0]));
+            CKE(xmy_m5hop64(1, BP_E, BP_O, BPP, true, dmask[M_SETUP0]));
+            CKE(fin(g64(1).nblocks, FIN_AUX, dmask[M_SETUP0]));
+        }
         CKR(pull());
         for (int r = 0; r < K; ++r)
             if (hmask[M_SETUP][r]) {
-                sl[r].bpp2 = h_aux(r);
+                sl[r].bpp2 = sl[r].form == DWF_SYSTEM_D ? h_aux(r) : sl[r].bnorm2;
                 sl[r].phase = PH_OUTER;
                 h_live(r) = 0;
                 h_iters(r) = 0;
@@ -584,7 +644,7 @@ class Engine : public EngineBase {
         int* m = dmask[M_OUTER];
         upload_mask(M_OUTER, [&](int r) { return sl[r].phase == PH_OUTER; });
         CKU();
-        CKE(outer_residual(m));
+        CKR(outer_residual_masked(M_OUTER));
         for (int r = 0; r < K; ++r)
             if (hmask[M_OUTER][r]) {
                 sl[r].restarts++;
@@ -600,7 +660,7 @@ class Engine : public EngineBase {
         CKU();
         if (nrev) {
             CKE(half_copy(c, w.f(YH_O), w.f(YH_E), K, dmask[M_REVERT], s));
-            CKE(outer_residual(dmask[M_REVERT]));
+            CKR(outer_residual_masked(M_REVERT));
             CKR(pull());
             for (int r = 0; r < K; ++r)
                 if (hmask[M_REVERT][r]) {
@@ -691,9 +751,20 @@ class Engine : public EngineBase {
 
     // ---- reconstruction y_e = b'_e - M5 D^EO y_o, x = S2 y, and |b - D x| / |b|
     int final_check() {
-        int* m = dmask[M_FINAL];
         upload_mask(M_FINAL, [&](int r) { return sl[r].phase == PH_FINAL; });
+        const int n0 = upload_mask(M_FIN0, [&](int r) { return hmask[M_FINAL][r] && sl[r].form == DWF_SYSTEM_D; });
         CKU();
+        const auto now = std::chrono::steady_clock::now();
+        // C C^dag w = b: the last outer residual was b - C C^dag w in FP64
+        for (int r = 0; r < K; ++r)
+            if (hmask[M_FINAL][r] && sl[r].form == DWF_SYSTEM_CCDAG) {
+                SlotCtl& q = sl[r];
+                q.true_res = q.schur_res;
+                q.phase = PH_DONE;
+                q.seconds = std::chrono::duration<double>(now - q.t0).count();
+            }
+        if (!n0) return DWF_OK;
+        int* m = dmask[M_FIN0];
         CKE(xmy_m5hop64(0, YH_O, BP_E, YH_E, false, m));
         CKE(local64(0, YH_E, TB_S2, BP_E, m));
         CKE(local64(1, YH_O, TB_S2, BP_O, m));
@@ -711,9 +782,8 @@ class Engine : public EngineBase {
         CKE(true_res(1, YH_E, B_O, BPP, m));
         CKE(fin(g64(1).nblocks, FIN_AUX, m));
         CKR(pull());
-        const auto now = std::chrono::steady_clock::now();
         for (int r = 0; r < K; ++r) {
-            if (!hmask[M_FINAL][r]) continue;
+            if (!hmask[M_FIN0][r]) continue;
             SlotCtl& q = sl[r];
             tr[r] += h_aux(r);
             q.true_res = q.bnorm2 > 0 ? sqrt(tr[r] / q.bnorm2) : sqrt(tr[r]);
@@ -730,7 +800,7 @@ class Engine : public EngineBase {
             }
         }
         // restore the pieces the reconstruction overwrote: b' and b''
-        int na = upload_mask(M_AGAIN, [&](int r) { return hmask[M_FINAL][r] && sl[r].phase == PH_OUTER; });
+        int na = upload_mask(M_AGAIN, [&](int r) { return hmask[M_FIN0][r] && sl[r].phase == PH_OUTER; });
         CKU();
         if (na) {
             CKE(local64(0, B_E, TB_S1, BP_E, dmask[M_AGAIN]));

@@ -118,3 +118,12 @@ def test_server_entry_points_without_a_device():
     assert L.dwf_server_stats_get(None, 0) == dwf.DWF_EINVAL
     s = dwf.server_stats(reset=True)
     assert s["completed"] == 0 and s["waits_for_memory"] == 0 and s["p99_latency"] == 0.0
+
+
+def test_unknown_system_rejected():
+    import paper_1101_0423_amd as dwf
+    L = dwf.lib()
+    p = dwf.default_params(system=2)
+    assert L.dwf_solve_dev(ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1), 1, ctypes.byref(p),
+                           None, None) == dwf.DWF_EINVAL
+    assert "system" in L.dwf_last_error().decode()

@@ -382,3 +382,28 @@ def test_cg_matches_dense_solve_and_full_cgne():
     assert i1["iters"] < i2["iters"]
     assert oracle.true_residual(*args, b, x1) < 1e-11
     assert rel(x1, x2) < 1e-9
+
+
+@pytest.mark.parametrize("kind", ["shamir", "general"])
+def test_ccdag_solve_equals_dense_solve(kind):
+    """The force solve C C^dag w = b (odd sites) by Algorithm 1 equals a LAPACK
+    solve of the dense C C^dag restricted to odd sites, which is Hermitian and
+    positive definite; even sites of w are zero."""
+    dims, ns, m0, mq = (2, 2, 2, 2), 4, 1.8, 0.1
+    U = inp.gauge_field(dims, 0.3, seed=23)
+    sigma, omega = weights(kind, ns)
+    shape = (2, 2, 2, 2, ns, 24)
+    a = (U, dims, ns, m0, mq, sigma, omega)
+    A = dense_matrix(lambda v: oracle.schur_c(*a, oracle.schur_cdag(*a, v)), shape)
+    par = parity_mask(dims).ravel()                       # per 4D site, [t][z][y][x] order
+    odd = np.repeat(par == 1, ns * 12)                    # per complex component
+    Ao = A[np.ix_(odd, odd)]
+    assert np.max(abs(Ao - Ao.conj().T)) < 1e-12 * np.max(abs(Ao))
+    assert np.min(np.linalg.eigvalsh(Ao)) > 0
+    b = rnd(dims, ns, 29)
+    wd = np.linalg.solve(Ao, inp.host_to_complex(b).ravel()[odd])
+    w, info = oracle.solve_ccdag(*a, b, tol=1e-14)
+    assert info["converged"]
+    wc = inp.host_to_complex(w).ravel()
+    assert np.all(wc[~odd] == 0)
+    assert np.linalg.norm(wc[odd] - wd) / np.linalg.norm(wd) < 1e-11
