@@ -84,10 +84,15 @@ def kernel_label(name):
     for key, label in KERNEL_KEYS:
         if key in name:
             return label
-    if "k_dwf" in name and "true, 3, dwf::ProLoad<dwf::FS>, dwf::EpiStore<dwf::FS" in name:
-        return "hop_eo_m5t"
-    if "k_dwf" in name and "true, 2, dwf::ProLoad<dwf::FS>, dwf::EpiStore<dwf::FS" in name:
-        return "hop_eo_m5"
+    if "k_dwf<" in name:
+        # k_dwf<Real, F, LF, NSMAX, HOP, MIXM, REGMIX, Pro, Epi>: the low-precision
+        # hop-only kernels A (M5^T, mode 3) and C (M5, mode 2) store their result
+        args = [a.strip() for a in name.split("k_dwf<", 1)[1].split(",")]
+        if len(args) >= 9 and args[0] == "float" and args[4] == "true" and "EpiStore" in name:
+            if args[5] == "3":
+                return "hop_eo_m5t"
+            if args[5] == "2":
+                return "hop_eo_m5"
     return name[:90]
 
 
@@ -378,6 +383,10 @@ def main():
         kp = dwf.default_params(inner_prec=prec, link_compress=lc, use_graph=0, maxiter=40)
         st, rc = ctx.solve_dev(bd, xd, params=kp)
         ms, by = ctx.time_kernels(params=kp, launches=5)
+        # counter calibration: the layout conversions of an M5 application move
+        # known bytes in each storage format (k_host_to_half / k_half_to_host)
+        for pr in (dwf.PREC_FP64, dwf.PREC_FP32, dwf.PREC_FP16):
+            ctx.apply_dev(dwf.OP_M5, bd, xd, prec=pr)
         print(json.dumps(dict(mode="kernels", workload=wname, ms={k: ms[k] for k in ms},
                               bytes={k: by[k] for k in by})), flush=True)
         ctx.close()
