@@ -18,6 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dwf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the pins' mutation test loads deliberately broken copies of the oracle
+_LIB_OVERRIDE = os.environ.get("DWF_ORACLE_LIB")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -40,9 +42,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB):
+                build()
+            L = ctypes.CDLL(_LIB)
         L.orc_gamma.argtypes = [ctypes.c_int, _dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_dw.argtypes = [_dp, _ip, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp]
