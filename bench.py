@@ -21,9 +21,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CG Gflops & HBM GB/s (16^3x32, Ns=16) + served solves/s, p99 latency"
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = {
-    "fp32": ("odwf_16x16x16x32_ns16", 1, 0),
-    "fp16": ("odwf_16x16x16x32_ns16_fp16", 2, 1),
+WORKLOADS = {  # name, inner precision, link_compress (-1: the library's default, 12-real)
+    "fp32": ("odwf_16x16x16x32_ns16", 1, -1),
+    "fp32-18real": ("odwf_16x16x16x32_ns16", 1, 0),
+    "fp16": ("odwf_16x16x16x32_ns16_fp16", 2, -1),
     "fp64": ("odwf_16x16x16x32_ns16", 0, 0),
 }
 KERNEL_SOURCES = ["paper_1101_0423_amd/csrc/dwf_device.h", "paper_1101_0423_amd/csrc/solver.hip"]
@@ -37,10 +38,11 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel, workload):
+def counter_traffic(kernel, workload, variant):
     """Counter-measured HBM bytes per launch from profiles/, or None when absent
-    or taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    or taken on different kernel sources.  variant: the --prec choice
+    (precision and link format)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{variant}.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -415,7 +417,7 @@ def main():
     dom = max(ms, key=ms.get)
     names = {"E": "cg_dir_m5t", "A": "hop_eo_m5t", "B": "hop_oe_g5_sub", "C": "hop_eo_m5", "D": "hop_oe_m5_cgupd"}
     achieved = by[dom] / (ms[dom] * 1e-3) * 1e-9
-    traffic = counter_traffic(names[dom], wname)
+    traffic = counter_traffic(names[dom], wname, args.prec)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=names[dom],
                     algorithmic_bytes_per_launch=by[dom], avg_launch_ms=round(ms[dom], 5))
@@ -429,7 +431,7 @@ def main():
                 config=dict(workload=f"{wname}: 16^3x32 lattice, Ns=16, m0=1.8, mq=0.01, sigma=omega~U[0.5,1.5], "
                                      f"SU(3) links eps=0.5, Gaussian RHS, tol 1e-10",
                             lattice=list(dims), Ns=ns, inner_prec=["fp64", "fp32", "fp16"][prec],
-                            link_real=12 if lc else 18, reliable_updates=True),
+                            link_real=18 if (lc == 0 or prec == 0) else 12, reliable_updates=True),
                 hbm_gbs=round(gbytes / elapsed, 1), iters=stats[-1][0]["iters"],
                 true_residual=stats[-1][0]["true_residual"], converged=ok,
                 roofline=roofline, kernels=kernels)

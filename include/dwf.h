@@ -96,7 +96,9 @@ typedef struct dwf_solve_params {
     int maxiter;             /* cap on inner iterations per right-hand side (default 50000) */
     int check_every;         /* inner iterations between host checks; 0 = adaptive        */
     int use_graph;           /* 1: capture inner iterations in a hipGraph (default)       */
-    int link_compress;       /* -1 auto (12-real for FP16), 0: 18-real, 1: 12-real links  */
+    int link_compress;       /* links in the inner solve: -1 auto (default: 12-real rows 0-1,
+                                row 2 = conj(row0 x row1), for FP32 and FP16 storage);
+                                0: 18-real (FP32); 1: 12-real.  FP64 always uses 18-real   */
     int use_guess;           /* 1: x holds an initial guess on entry; 0: start from zero  */
     int debug_stall_after;   /* test hook: >0 declares reliable updates stalled after this
                                 many restarts, forcing the defect-correction fallback     */

@@ -251,20 +251,40 @@ __device__ __forceinline__ void su3_third_row(Real* u) {
 
 // stage(lds, site0, nsites, tid, T, sc): the 8 links of nsites sites, link l
 // (= 8 * site + entry) multiplied by sc(l), as row-major 3x3 in LDS.
+// 18-real links: a site's 8 links are 8 x 18 contiguous reals (a multiple of
+// 16 bytes), read as 16-byte vectors, DWF_STAGE_BATCH per thread in flight
+// before any is written to LDS.
+constexpr int DWF_STAGE_BATCH = 4;
+
+template <class Real, class V, int PER, class Sc>
+__device__ __forceinline__ void stage18(const V* __restrict__ src, Real* lds, int nsites, int tid, int T,
+                                        const Sc& sc) {
+    const int nv = nsites * 8 * 18 / PER;  // vectors of PER reals
+    for (int base = tid; base < nv; base += DWF_STAGE_BATCH * T) {
+        V q[DWF_STAGE_BATCH];
+#pragma unroll
+        for (int k = 0; k < DWF_STAGE_BATCH; ++k)
+            if (base + k * T < nv) q[k] = src[base + k * T];
+#pragma unroll
+        for (int k = 0; k < DWF_STAGE_BATCH; ++k) {
+            const int i = base + k * T;
+            if (i >= nv) break;
+            const Real* qv = (const Real*)&q[k];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int e = i * PER + j, l = e / 18, c = e - 18 * l;
+                lds[LdsLink<Real>::at(l) + c] = sc(l) * qv[j];
+            }
+        }
+    }
+}
+
 struct LinkD18 {
     using real = double;
     const double* p;  // [h4][8][18]
     template <class Sc>
     __device__ __forceinline__ void stage(double* lds, long site0, int nsites, int tid, int T, const Sc& sc) const {
-        const double2* src = (const double2*)(p + site0 * 8 * 18);
-        int n2 = nsites * 8 * 9;
-        for (int i = tid; i < n2; i += T) {
-            double2 q = src[i];
-            int l = i / 9, c = i - 9 * l;
-            double f = sc(l);
-            lds[LdsLink<double>::at(l) + 2 * c] = f * q.x;
-            lds[LdsLink<double>::at(l) + 2 * c + 1] = f * q.y;
-        }
+        stage18<double, double2, 2>((const double2*)(p + site0 * 8 * 18), lds, nsites, tid, T, sc);
     }
 };
 
@@ -273,15 +293,7 @@ struct LinkS18 {
     const float* p;  // [h4][8][18]
     template <class Sc>
     __device__ __forceinline__ void stage(float* lds, long site0, int nsites, int tid, int T, const Sc& sc) const {
-        const float2* src = (const float2*)(p + site0 * 8 * 18);
-        int n2 = nsites * 8 * 9;
-        for (int i = tid; i < n2; i += T) {
-            int l = i / 9, c = i - 9 * l;
-            float2 q = src[i];
-            float f = sc(l);
-            lds[LdsLink<float>::at(l) + 2 * c] = f * q.x;
-            lds[LdsLink<float>::at(l) + 2 * c + 1] = f * q.y;
-        }
+        stage18<float, float4, 4>((const float4*)(p + site0 * 8 * 18), lds, nsites, tid, T, sc);
     }
 };
 

@@ -61,7 +61,7 @@ double bytes_per_iter(const dwf_ctx* c, int inner_prec, int link_fmt) {
 int link_format(const dwf_solve_params& p) {
     switch (p.inner_prec) {
         case DWF_PREC_FP64: return LINK_D18;
-        case DWF_PREC_FP32: return p.link_compress == 1 ? LINK_S12 : LINK_S18;
+        case DWF_PREC_FP32: return p.link_compress == 0 ? LINK_S18 : LINK_S12;  // auto: 12-real
         default: return LINK_H12;
     }
 }
@@ -993,7 +993,7 @@ int make_engine(dwf_ctx* c, const dwf_solve_params& p, int K, hipStream_t s, std
                                                   LinkD18{c->links[0][LINK_D18].as<double>()},
                                                   LinkD18{c->links[1][LINK_D18].as<double>()}, out);
         case DWF_PREC_FP32:
-            if (p.link_compress == 1)
+            if (p.link_compress != 0)
                 return build<float, FS, FS, LinkS12>(c, DWF_PREC_FP32, LINK_S12, K, s,
                                                      LinkS12{c->links[0][LINK_S12].as<float>()},
                                                      LinkS12{c->links[1][LINK_S12].as<float>()}, out);

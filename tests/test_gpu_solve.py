@@ -156,8 +156,9 @@ def _golden(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("name,prec,lc", [("odwf_16x16x16x32_ns16", 1, 0), ("odwf_16x16x16x32_ns16", 2, 1)],
-                         ids=["fp32", "fp16-12real"])
+@pytest.mark.parametrize("name,prec,lc", [("odwf_16x16x16x32_ns16", 1, -1), ("odwf_16x16x16x32_ns16", 1, 0),
+                                          ("odwf_16x16x16x32_ns16", 2, -1)],
+                         ids=["fp32-12real", "fp32-18real", "fp16-12real"])
 def test_full_size_solve(name, prec, lc):
     """The primary workload (16^3x32, Ns = 16) in the launch configuration of
     the benchmark: true residual with the oracle's operator over the whole
