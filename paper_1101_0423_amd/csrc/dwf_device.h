@@ -56,6 +56,15 @@ struct FD {  // FP64 storage and arithmetic
     __device__ __forceinline__ void gather(int rhs, long i, int s, R* v) const {
         load(rhs, i, s, v);
     }
+    // two-stage gather: fetch issues the loads, unpack consumes them, so that
+    // a hop can keep the next neighbour's loads in flight meanwhile
+    struct Raw { double v[24]; };
+    __device__ __forceinline__ void fetch(int rhs, long i, int s, Raw& r) const { load(rhs, i, s, r.v); }
+    template <class R>
+    __device__ __forceinline__ void unpack(const Raw& r, R* v) const {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) v[k] = (R)r.v[k];
+    }
     __device__ __forceinline__ void load(int rhs, long i, int s, double* v) const {
         const double2* q = at(rhs, i, s);
 #pragma unroll
@@ -105,6 +114,12 @@ struct FS {  // FP32 storage
         }
     }
     __device__ __forceinline__ void gather(int rhs, long i, int s, float* v) const { load(rhs, i, s, v); }
+    struct Raw { float v[24]; };
+    __device__ __forceinline__ void fetch(int rhs, long i, int s, Raw& r) const { load(rhs, i, s, r.v); }
+    __device__ __forceinline__ void unpack(const Raw& r, float* v) const {
+#pragma unroll
+        for (int k = 0; k < 24; ++k) v[k] = r.v[k];
+    }
     __device__ __forceinline__ void store(int rhs, long i, int s, const float* v) const {
         float4* q = const_cast<float4*>(at(rhs, i, s));
 #pragma unroll
@@ -160,6 +175,26 @@ struct FH {  // binary16 storage with one FP32 scale per 5D site; FP32 arithmeti
     template <class R>
     __device__ __forceinline__ void gather(int rhs, long i, int s, R* v) const {
         load(rhs, i, s, v);
+    }
+    // two-stage gather: the raw 16-byte vectors and the scale, converted in unpack
+    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+    struct Raw {
+        u4v a[3];
+        float n;
+    };
+    __device__ __forceinline__ void fetch(int rhs, long i, int s, Raw& r) const {
+        const u4v* q = (const u4v*)at(rhs, i, s);
+        r.n = nrm[rhs * nrstride + i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) r.a[j] = q[j * ns];
+    }
+    __device__ __forceinline__ void unpack(const Raw& r, float* v) const {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            half8_t h = __builtin_bit_cast(half8_t, r.a[j]);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[8 * j + k] = (float)h[k] * r.n;
+        }
     }
     // NT: non-temporal (streaming) access, as for FS
     template <bool NT = false>
@@ -397,10 +432,10 @@ __device__ __forceinline__ int block_of(int L, const Geom& g) {
 // h0, h1; U multiplies only those and the lower two are rebuilt from U h.
 // ---------------------------------------------------------------------------
 
+// Spin projection: the two components h0, h1 that fix (1 + SIG gamma_MU) psi.
 template <int MU, int SIG, class Real>
-__device__ __forceinline__ void hop_dir(const Real* __restrict__ psi, const Real* __restrict__ U,
-                                        Real* __restrict__ acc) {
-    Real h0[6], h1[6];
+__device__ __forceinline__ void hop_proj(const Real* __restrict__ psi, Real* __restrict__ h0,
+                                         Real* __restrict__ h1) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const Real p0r = psi[2 * a], p0i = psi[2 * a + 1];
@@ -421,17 +456,50 @@ __device__ __forceinline__ void hop_dir(const Real* __restrict__ psi, const Real
             h1[2 * a] = p1r + SIG * p3r; h1[2 * a + 1] = p1i + SIG * p3i;
         }
     }
+}
+
+// acc += (1 + SIG gamma_MU) U psi from the projected h0, h1: colour multiply
+// of the two components, then the lower two rebuilt from them.  CHAIN: each
+// real part is one chain of fused multiply-adds seeded by its first product
+// (no "+ 0", which IEEE signed zeros keep the compiler from removing), and
+// FIRST sets acc instead of adding to it; otherwise the products are summed
+// per complex term into accumulators that start at zero.
+template <int MU, int SIG, bool FIRST, bool CHAIN, class Real>
+__device__ __forceinline__ void hop_mul(const Real* __restrict__ h0, const Real* __restrict__ h1,
+                                        const Real* __restrict__ U, Real* __restrict__ acc) {
     Real u0[6], u1[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        Real r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+        const Real* Ua = U + 6 * a;
+        Real r0, i0, r1, i1;
+        if constexpr (CHAIN) {
+            r0 = Ua[0] * h0[0]; i0 = Ua[0] * h0[1]; r1 = Ua[0] * h1[0]; i1 = Ua[0] * h1[1];
+            r0 = fma(-Ua[1], h0[1], r0);
+            i0 = fma(Ua[1], h0[0], i0);
+            r1 = fma(-Ua[1], h1[1], r1);
+            i1 = fma(Ua[1], h1[0], i1);
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const Real ur = U[2 * (3 * a + b)], ui = U[2 * (3 * a + b) + 1];
-            r0 += ur * h0[2 * b] - ui * h0[2 * b + 1];
-            i0 += ur * h0[2 * b + 1] + ui * h0[2 * b];
-            r1 += ur * h1[2 * b] - ui * h1[2 * b + 1];
-            i1 += ur * h1[2 * b + 1] + ui * h1[2 * b];
+            for (int b = 1; b < 3; ++b) {
+                const Real ur = Ua[2 * b], ui = Ua[2 * b + 1];
+                r0 = fma(ur, h0[2 * b], r0);
+                r0 = fma(-ui, h0[2 * b + 1], r0);
+                i0 = fma(ur, h0[2 * b + 1], i0);
+                i0 = fma(ui, h0[2 * b], i0);
+                r1 = fma(ur, h1[2 * b], r1);
+                r1 = fma(-ui, h1[2 * b + 1], r1);
+                i1 = fma(ur, h1[2 * b + 1], i1);
+                i1 = fma(ui, h1[2 * b], i1);
+            }
+        } else {
+            r0 = 0; i0 = 0; r1 = 0; i1 = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const Real ur = Ua[2 * b], ui = Ua[2 * b + 1];
+                r0 += ur * h0[2 * b] - ui * h0[2 * b + 1];
+                i0 += ur * h0[2 * b + 1] + ui * h0[2 * b];
+                r1 += ur * h1[2 * b] - ui * h1[2 * b + 1];
+                i1 += ur * h1[2 * b + 1] + ui * h1[2 * b];
+            }
         }
         u0[2 * a] = r0; u0[2 * a + 1] = i0;
         u1[2 * a] = r1; u1[2 * a + 1] = i1;
@@ -439,8 +507,6 @@ __device__ __forceinline__ void hop_dir(const Real* __restrict__ psi, const Real
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const Real r0 = u0[2 * a], i0 = u0[2 * a + 1], r1 = u1[2 * a], i1 = u1[2 * a + 1];
-        acc[2 * a] += r0; acc[2 * a + 1] += i0;
-        acc[2 * (3 + a)] += r1; acc[2 * (3 + a) + 1] += i1;
         Real c2r, c2i, c3r, c3i;
         if (MU == 0) {  // c2 = SIG i u1, c3 = SIG i u0
             c2r = -SIG * i1; c2i = SIG * r1; c3r = -SIG * i0; c3i = SIG * r0;
@@ -451,8 +517,17 @@ __device__ __forceinline__ void hop_dir(const Real* __restrict__ psi, const Real
         } else {  // c2 = SIG u0, c3 = SIG u1
             c2r = SIG * r0; c2i = SIG * i0; c3r = SIG * r1; c3i = SIG * i1;
         }
-        acc[2 * (6 + a)] += c2r; acc[2 * (6 + a) + 1] += c2i;
-        acc[2 * (9 + a)] += c3r; acc[2 * (9 + a) + 1] += c3i;
+        if (FIRST) {  // the first direction sets the accumulator
+            acc[2 * a] = r0; acc[2 * a + 1] = i0;
+            acc[2 * (3 + a)] = r1; acc[2 * (3 + a) + 1] = i1;
+            acc[2 * (6 + a)] = c2r; acc[2 * (6 + a) + 1] = c2i;
+            acc[2 * (9 + a)] = c3r; acc[2 * (9 + a) + 1] = c3i;
+        } else {
+            acc[2 * a] += r0; acc[2 * a + 1] += i0;
+            acc[2 * (3 + a)] += r1; acc[2 * (3 + a) + 1] += i1;
+            acc[2 * (6 + a)] += c2r; acc[2 * (6 + a) + 1] += c2i;
+            acc[2 * (9 + a)] += c3r; acc[2 * (9 + a) + 1] += c3i;
+        }
     }
 }
 
@@ -485,30 +560,47 @@ __device__ __forceinline__ void neighbours(const Geom& g, int h4, int par, int* 
 
 // The 8 directions of Eq. (14) for one (site, s) lane.  The staged links
 // already carry the factor -1/2 (and the sign of links that cross an
-// antiperiodic time boundary).  (Keeping two directions' loads in flight per
-// wave costs a wave of occupancy and measured slower on gfx950.)
-template <class Real, class F>
+// antiperiodic time boundary).  PIPE: software pipelined; once a direction's
+// input is projected, its registers take the next neighbour's loads, which
+// are in flight while the colour multiply of this direction runs (the
+// scheduling barriers keep the compiler from moving them across), and the
+// multiply uses fused chains (hop_mul CHAIN).  Otherwise each direction loads,
+// waits and multiplies in turn.
+template <class Real, bool PIPE, class F>
 __device__ __forceinline__ void hop_site(const F& in, int rhs, int s, int Ns, const int* nb,
                                          const Real* __restrict__ lk, Real* acc) {
-#pragma unroll
-    for (int k = 0; k < 24; ++k) acc[k] = 0;
     constexpr int LS = LdsLink<Real>::STR;
-    Real U[18];
-    Real pa[24];
-#define DWF_STEP(MU, SIG, L)                                                   \
-    {                                                                          \
-        in.gather(rhs, (long)nb[L] * Ns + s, s, pa);                           \
-        _Pragma("unroll") for (int k = 0; k < 18; ++k) U[k] = lk[(L) * LS + k]; \
-        hop_dir<MU, SIG>(pa, U, acc);                                          \
+    if (!PIPE)
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = 0;
+    typename F::Raw raw;
+    if (PIPE) in.fetch(rhs, (long)nb[0] * Ns + s, s, raw);
+#define DWF_STEP(MU, SIG, L, NEXT)                                               \
+    {                                                                            \
+        if (!PIPE) in.fetch(rhs, (long)nb[L] * Ns + s, s, raw);                  \
+        Real h0[6], h1[6];                                                       \
+        {                                                                        \
+            Real pa[24];                                                         \
+            in.unpack(raw, pa);                                                  \
+            hop_proj<MU, SIG>(pa, h0, h1);                                       \
+        }                                                                        \
+        if (PIPE) {                                                              \
+            __builtin_amdgcn_sched_barrier(0);                                   \
+            if ((NEXT) >= 0) in.fetch(rhs, (long)nb[(NEXT) & 7] * Ns + s, s, raw); \
+            __builtin_amdgcn_sched_barrier(0);                                   \
+        }                                                                        \
+        Real U[18];                                                              \
+        _Pragma("unroll") for (int k = 0; k < 18; ++k) U[k] = lk[(L) * LS + k];  \
+        hop_mul<MU, SIG, (L) == 0 && PIPE, PIPE>(h0, h1, U, acc);                 \
     }
-    DWF_STEP(0, -1, 0)
-    DWF_STEP(0, +1, 4)
-    DWF_STEP(1, -1, 1)
-    DWF_STEP(1, +1, 5)
-    DWF_STEP(2, -1, 2)
-    DWF_STEP(2, +1, 6)
-    DWF_STEP(3, -1, 3)
-    DWF_STEP(3, +1, 7)
+    DWF_STEP(0, -1, 0, 4)
+    DWF_STEP(0, +1, 4, 1)
+    DWF_STEP(1, -1, 1, 5)
+    DWF_STEP(1, +1, 5, 2)
+    DWF_STEP(2, -1, 2, 6)
+    DWF_STEP(2, +1, 6, 3)
+    DWF_STEP(3, -1, 3, 7)
+    DWF_STEP(3, +1, 7, -1)
 #undef DWF_STEP
 }
 
@@ -694,6 +786,7 @@ __device__ __forceinline__ void mix_reg16(Real* v, const Real* __restrict__ C, i
     const int k = REV ? 15 - s : s;
     const Real F = C[k], G = C[16 + k], B = C[32 + k], P = C[48 + k], Q = C[64 + k], O = C[80 + k];
     const Real F0 = C[0], G0 = C[16];
+    const Real Fk = k ? F : (Real)0;  // the sweep starts at k = 1
     // scan multipliers: A_d(k) = prod_{j = k-d+1..k} (-G_j), zero where k < d
     const Real A1 = k ? -G : (Real)0;
     const Real A2 = A1 * rshift<REV, 1>(A1);
@@ -707,7 +800,7 @@ __device__ __forceinline__ void mix_reg16(Real* v, const Real* __restrict__ C, i
             x = h;
         else
             x = P * h + Q * rprev<REV>(h);  // Y^T sqrt(w)^-1 h
-        Real al = k ? F * x : (Real)0;
+        Real al = Fk * x;
         al += A1 * rshift<REV, 1>(al);
         al += A2 * rshift<REV, 2>(al);
         al += A4 * rshift<REV, 4>(al);
@@ -769,6 +862,17 @@ __host__ __device__ inline size_t kernel_smem(int G, int Ns, bool hop, bool mix)
     b += 16 * sizeof(double);
     return b;
 }
+
+// Which hop form a kernel uses (hop_site's PIPE).  The pipelined form with
+// fused multiply-add chains takes fewer instructions and registers; it is
+// faster everywhere on gfx950 except in the FP32 kernel D, whose streamed CG
+// vectors already fill the register budget, which keeps the sequential form.
+template <class A, class B, class C> struct EpiCgD;
+template <class E> struct IsCgD { static constexpr bool value = false; };
+template <class A, class B, class C> struct IsCgD<EpiCgD<A, B, C>> { static constexpr bool value = true; };
+template <class F, class E> struct HopPipe {
+    static constexpr bool value = !(std::is_same<F, FS>::value && IsCgD<E>::value);
+};
 
 template <class Real, class F, class LF, int NSMAX, bool HOP, int MIXM, bool REGMIX, class Pro, class Epi>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<F, FS>::value ? 4 : 1)))
@@ -844,7 +948,7 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
         Real v[24];
         if (act) {
             if constexpr (HOP)
-                hop_site<Real>(in, rhs, s, Ns, nb, lk + sl * LdsLink<Real>::SITE, v);
+                hop_site<Real, HopPipe<F, Epi>::value>(in, rhs, s, Ns, nb, lk + sl * LdsLink<Real>::SITE, v);
             else
                 pro(rhs, i5, s, v);
         } else {
