@@ -84,6 +84,14 @@ def lib():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is not built; run paper_1101_0423_amd/build.py "
                           "(or __graft_entry__.build())")
+    # One HIP runtime per process.  PyTorch ships its own HIP and HSA
+    # runtimes; loaded first, they also serve libdwf.so (same sonames).  Loaded
+    # after libdwf.so has pulled in the system ones, a second HSA runtime
+    # cannot open the GPU and torch finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(_LIB_PATH)
     vp = ctypes.c_void_p
     L.dwf_default_opts.argtypes = [ctypes.POINTER(Opts)]

@@ -229,8 +229,13 @@ hipError_t launch_kernel(void (*kern)(Args...), dim3 grid, dim3 block, size_t sm
 }
 
 template <class Real, class F, class LF, bool HOP, int MIXM, class Pro, class Epi>
-hipError_t launch_dwf(const Geom& g, const F& in, const LF& links, const Real* table, const Pro& pro,
+hipError_t launch_dwf(const Geom& g0, const F& in, const LF& links, const Real* table, const Pro& pro,
                       const Epi& epi, KOpt o, hipStream_t st) {
+    // The t-fastest block order serves the hop's neighbour re-reads from L2; a
+    // kernel without a hop streams its blocks in plain order (each XCD one
+    // contiguous range), which measured 7% faster for the streaming kernels.
+    Geom g = g0;
+    if constexpr (!HOP) g.nsb = 0;
     int T = round_up(g.G * g.Ns, 64);
     // Ns = 16 with a recurrence-form M5 / M5^T: applied in registers, no LDS buffer
     constexpr bool STRUCT = MIXM == MIX_SA || MIXM == MIX_AS;

@@ -127,3 +127,22 @@ def test_unknown_system_rejected():
     assert L.dwf_solve_dev(ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.c_void_p(1), 1, ctypes.byref(p),
                            None, None) == dwf.DWF_EINVAL
     assert "system" in L.dwf_last_error().decode()
+
+
+def test_one_hip_runtime_per_process():
+    """The binding loads torch (when installed) before libdwf.so, so that both
+    use the HIP and HSA runtimes torch ships: a process that had loaded the
+    system runtimes first would hold two HSA runtimes, and the second cannot
+    open the GPU (torch then reports no device)."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1101_0423_amd as dwf\n"
+            "dwf.lib()\n"
+            "import torch\n"
+            "m = sorted({l.split()[-1] for l in open('/proc/self/maps')"
+            " if 'libamdhip64' in l or 'libhsa-runtime64' in l})\n"
+            "print('\\n'.join(m))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    libs = out.stdout.split()
+    assert sum("libamdhip64" in p for p in libs) == 1, libs
+    assert sum("libhsa-runtime64" in p for p in libs) == 1, libs
