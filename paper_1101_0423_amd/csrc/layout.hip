@@ -168,55 +168,66 @@ __global__ void k_pack_links(const double* __restrict__ gauge, Dims d, int par, 
     }
 }
 
-__global__ void k_finish(const double* __restrict__ partials, int nblocks, int nrhs, CgState st, int mode,
-                         const int* __restrict__ mask) {
-    __shared__ double red[16];
-    for (int r = 0; r < nrhs; ++r) {
-        if ((mode == FIN_ALPHA || mode == FIN_BETA) && !st.live[r]) continue;
-        if ((mode == FIN_AUX || mode == FIN_OUTER) && mask && !mask[r]) continue;
-        double s = 0;
-        for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += partials[(long)r * nblocks + i];
-        double tot = block_sum(s, red);
-        if (threadIdx.x == 0) {
-            if (mode == FIN_AUX) {
-                st.aux[r] = tot;
-            } else if (mode == FIN_OUTER) {
-                st.aux[r] = tot;
-                st.rr[r] = tot;
-            } else if (mode == FIN_ALPHA) {
-                st.uu[r] = tot;
-                if (!(tot > 0.0) || !isfinite(tot)) {
-                    st.status[r] = 2;
-                    st.live[r] = 0;
-                    if (st.live_host) st.live_host[r] = 0;
-                } else {
-                    st.alpha[r] = st.rr[r] / tot;
-                }
-            } else if (mode == FIN_BETA) {
-                if (!isfinite(tot)) {
-                    st.status[r] = 2;
-                    st.live[r] = 0;
-                    if (st.live_host) st.live_host[r] = 0;
-                } else {
-                    st.beta[r] = tot / st.rr[r];
-                    st.ecr[r] = 1.0;
-                    st.rr[r] = tot;
-                    st.iters[r] += 1;
-                    if (tot <= st.rr_target[r]) {
-                        st.live[r] = 0;
-                        st.status[r] = 1;
-                    } else if (tot > 1e8 * st.aux[r]) {  // |r| grew 1e4-fold since the restart
-                        st.live[r] = 0;
-                        st.status[r] = 4;
-                    } else if (st.iters[r] >= st.maxiter[r]) {
-                        st.live[r] = 0;
-                        st.status[r] = 3;
-                    }
-                    if (st.live_host && !st.live[r]) st.live_host[r] = 0;
-                }
-            }
+constexpr int kFinT = 512;
+
+// One workgroup per right-hand side: its block sums in a fixed order (thread
+// i takes i, i + T, i + 2T, ... into four accumulators, then the block tree),
+// so a right-hand side's result does not depend on how many others share the
+// launch, and the sums of different right-hand sides run in parallel.
+__global__ void __launch_bounds__(kFinT) k_finish(const double* __restrict__ partials, int nblocks, CgState st,
+                                                  int mode, const int* __restrict__ mask) {
+    __shared__ double red[kFinT / 64];
+    const int r = blockIdx.x;
+    if ((mode == FIN_ALPHA || mode == FIN_BETA) && !st.live[r]) return;
+    if ((mode == FIN_AUX || mode == FIN_OUTER) && mask && !mask[r]) return;
+    const double* __restrict__ pr = partials + (long)r * nblocks;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int i = threadIdx.x;
+    for (; i + 3 * kFinT < nblocks; i += 4 * kFinT) {
+        s0 += pr[i];
+        s1 += pr[i + kFinT];
+        s2 += pr[i + 2 * kFinT];
+        s3 += pr[i + 3 * kFinT];
+    }
+    for (; i < nblocks; i += kFinT) s0 += pr[i];
+    const double tot = block_sum((s0 + s1) + (s2 + s3), red);
+    if (threadIdx.x != 0) return;
+    if (mode == FIN_AUX) {
+        st.aux[r] = tot;
+    } else if (mode == FIN_OUTER) {
+        st.aux[r] = tot;
+        st.rr[r] = tot;
+    } else if (mode == FIN_ALPHA) {
+        st.uu[r] = tot;
+        if (!(tot > 0.0) || !isfinite(tot)) {
+            st.status[r] = 2;
+            st.live[r] = 0;
+            if (st.live_host) st.live_host[r] = 0;
+        } else {
+            st.alpha[r] = st.rr[r] / tot;
         }
-        __syncthreads();
+    } else if (mode == FIN_BETA) {
+        if (!isfinite(tot)) {
+            st.status[r] = 2;
+            st.live[r] = 0;
+            if (st.live_host) st.live_host[r] = 0;
+        } else {
+            st.beta[r] = tot / st.rr[r];
+            st.ecr[r] = 1.0;
+            st.rr[r] = tot;
+            st.iters[r] += 1;
+            if (tot <= st.rr_target[r]) {
+                st.live[r] = 0;
+                st.status[r] = 1;
+            } else if (tot > 1e8 * st.aux[r]) {  // |r| grew 1e4-fold since the restart
+                st.live[r] = 0;
+                st.status[r] = 4;
+            } else if (st.iters[r] >= st.maxiter[r]) {
+                st.live[r] = 0;
+                st.status[r] = 3;
+            }
+            if (st.live_host && !st.live[r]) st.live_host[r] = 0;
+        }
     }
 }
 
@@ -224,7 +235,7 @@ __global__ void k_finish(const double* __restrict__ partials, int nblocks, int n
 
 hipError_t launch_finish(const double* partials, int nblocks, int nrhs, CgState st, int mode, hipStream_t s,
                          const int* mask) {
-    return launch_kernel(k_finish, dim3(1), dim3(256), 0, s, partials, nblocks, nrhs, st, mode, mask);
+    return launch_kernel(k_finish, dim3((unsigned)nrhs), dim3(kFinT), 0, s, partials, nblocks, st, mode, mask);
 }
 
 hipError_t host_to_half(const dwf_ctx* c, const double* host, int nrhs, HalfField& even, HalfField& odd,
