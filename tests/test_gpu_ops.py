@@ -168,3 +168,86 @@ def test_full_size_operator_parity():
                 assert max_rel(got, exp) <= 4 * TOL[prec]
     finally:
         ctx.close()
+
+
+def _cplx(a, ns):
+    """host spinor -> complex [t][z][y][x][s][spin][colour]"""
+    z = inp.host_to_complex(a)
+    return z.reshape(z.shape[:-1] + (4, 3))
+
+
+def _real(z):
+    return inp.complex_to_host(z.reshape(z.shape[:-2] + (12,)))
+
+
+def _gammas():
+    """Chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] (mu = 0, 1, 2 for
+    k = 1, 2, 3), gamma_4 = [[0, 1], [1, 0]] (mu = 3)."""
+    sig = [np.array([[0, 1], [1, 0]], complex), np.array([[0, -1j], [1j, 0]]), np.array([[1, 0], [0, -1]], complex)]
+    z = np.zeros((2, 2), complex)
+    g = [np.block([[z, -1j * s], [1j * s, z]]) for s in sig]
+    g.append(np.block([[z, np.eye(2)], [np.eye(2), z]]))
+    return g
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("bct", [1.0, -1.0], ids=["periodic", "antiperiodic"])
+def test_unit_link_plane_waves_on_gpu(prec, bct):
+    """With U = 1 the GPU's D_w (Eq. (2)) maps a plane wave e^{ipx} chi_s to
+    [(4 - m0 - sum_mu cos p_mu) + i sum_mu gamma_mu sin p_mu] e^{ipx} chi_s on
+    every slice: the closed form, written out here, not taken from the oracle.
+    Antiperiodic time shifts p_t by pi / Lt."""
+    import paper_1101_0423_amd as dwf
+    dims, ns, m0 = (4, 6, 2, 8), 3, 1.3
+    lx, ly, lz, lt = dims
+    print(f"[ops] plane waves prec={prec} bct={bct}", flush=True)
+    c = dwf.Context(inp.unit_gauge(dims), dims, ns, m0, 0.1, np.zeros(ns), np.ones(ns), antiperiodic_t=bct < 0)
+    try:
+        t, z, y, x = np.meshgrid(range(lt), range(lz), range(ly), range(lx), indexing="ij")
+        g = _gammas()
+        rng = np.random.default_rng(17)
+        shift = 0.5 if bct < 0 else 0.0
+        for n in [(1, 2, 1, 3), (0, 1, 0, 0), (3, 5, 1, 7)]:
+            p = [2 * np.pi * n[0] / lx, 2 * np.pi * n[1] / ly, 2 * np.pi * n[2] / lz, 2 * np.pi * (n[3] + shift) / lt]
+            phase = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))[..., None, None, None]
+            chi = rng.normal(size=(ns, 4, 3)) + 1j * rng.normal(size=(ns, 4, 3))
+            W = 4 - m0 - sum(np.cos(pm) for pm in p)
+            M = W * np.eye(4) + 1j * sum(g[m] * np.sin(p[m]) for m in range(4))
+            exp = phase * np.einsum("ij,sjc->sic", M, chi)
+            got = _cplx(c.apply(dwf.OP_DW, _real(phase * chi), prec=prec), ns)
+            err = np.linalg.norm(got - exp) / np.linalg.norm(exp)
+            assert err <= TOL[prec], (n, err)
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_gauge_covariance_on_gpu(prec):
+    """D_w[U^g](g psi) = g D_w[U] psi and the same for the Schur operator C,
+    U^g_mu(x) = g(x) U_mu(x) g(x + mu)^dag, on the GPU alone (two contexts,
+    antiperiodic time, ragged workgroups)."""
+    import paper_1101_0423_amd as dwf
+    P = PROBS["ragged"]
+    print(f"[ops] gauge covariance prec={prec}", flush=True)
+    gt = inp.gauge_transform(P.dims, 0.7, seed=41)
+    Uc = P.U[..., 0] + 1j * P.U[..., 1]
+    Ug = np.empty_like(Uc)
+    for mu in range(4):
+        gshift = np.roll(gt, -1, axis=3 - mu)  # g(x + mu); array axes are [t][z][y][x]
+        Ug[..., mu, :, :] = gt @ Uc[..., mu, :, :] @ np.conj(np.swapaxes(gshift, -1, -2))
+    Ugr = np.stack([Ug.real, Ug.imag], axis=-1)
+
+    def rot(a):
+        return _real(np.einsum("tzyxab,tzyxsib->tzyxsia", gt, _cplx(a, P.ns)))
+
+    c1 = P.context()
+    c2 = dwf.Context(Ugr, *P.args, antiperiodic_t=True)
+    try:
+        psi = P.b
+        for op in (dwf.OP_DW, dwf.OP_C):
+            lhs = c2.apply(op, rot(psi), prec=prec)
+            rhs = rot(c1.apply(op, psi, prec=prec))
+            assert rel(lhs, rhs) <= 2 * TOL[prec], (op, rel(lhs, rhs))
+    finally:
+        c1.close()
+        c2.close()
