@@ -116,9 +116,25 @@ dwf::Geom dwf_ctx::geom(int out_parity, bool fp64) const {
     const long V3h = V4h / dims[3];
     g.nsb = 0;
     g.tchunk = 0;
+    g.nsb0 = 0;
+    g.tilew = 0;
     if (g.xcd && V3h % g.G == 0) {
         g.nsb = (int)(V3h / g.G);
         g.tchunk = dims[3] % 8 == 0 ? dims[3] / 8 : dims[3];
+        // Tile the z-planes when the t-fastest order would put a block's +-z
+        // neighbour more than 64 workgroups back (an XCD holds about 128 at
+        // once): 24^3 planes (18 blocks, 6 t-slices per chunk) gain 2-8% per
+        // hop kernel, 16^3 planes (8 blocks, 4 t-slices) lose with tiles.
+        const long plane = (long)g.Lxh * g.Ly;
+        if (plane % g.G == 0) {
+            g.nsb0 = (int)(plane / g.G);
+            if ((long)g.nsb0 * g.tchunk > 64)
+                for (int w = 6; w >= 2; --w)
+                    if (g.nsb0 % w == 0) {
+                        g.tilew = w;
+                        break;
+                    }
+        }
     }
     return g;
 }

@@ -398,6 +398,8 @@ struct Geom {
     int xcd;       // 1: map consecutive lattice blocks onto one XCD
     int nsb;       // > 0: workgroups go t-fastest: blocks per t-slice (V3h / G) ...
     int tchunk;    // ... in chunks of tchunk t-slices (one chunk per XCD)
+    int nsb0;      // blocks per z-plane of a t-slice (whole planes only)
+    int tilew;     // > 0: z-plane blocks walked in tiles of tilew (block_of)
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
@@ -415,12 +417,22 @@ __device__ __forceinline__ int xcd_remap(int b, int nb, int on) {
 // Lattice block of a workgroup's position L in the (XCD-remapped) order.  With
 // g.nsb > 0 the order runs t-fastest through every chunk of tchunk t-slices:
 // L = (chunk, spatial block, t in chunk), so the +-t neighbours of a block
-// were read one workgroup earlier and the +-z ones a few spatial blocks
-// earlier, both still in the XCD's L2.  A bijection on [0, nblocks).
+// were read one workgroup earlier and the +-z ones nsb0 * tchunk workgroups
+// earlier, both still in the XCD's L2.  Where that distance is large (big
+// z-planes) the blocks of a z-plane are cut into tiles of tilew and the order
+// is L = (chunk, tile, z, t in chunk, block in tile): +-y neighbours sit in
+// the same or the previous workgroup, +-t tilew and +-z tilew * tchunk back.
+// A bijection on [0, nblocks).
 __device__ __forceinline__ int block_of(int L, const Geom& g) {
     if (g.nsb <= 0) return L;
     const int per = g.nsb * g.tchunk;
     const int chunk = L / per, rem = L - chunk * per;
+    if (g.tilew > 0) {
+        const int i = rem % g.tilew, r2 = rem / g.tilew;
+        const int tt = r2 % g.tchunk, r3 = r2 / g.tchunk;
+        const int z = r3 % g.Lz, j = r3 / g.Lz;
+        return (chunk * g.tchunk + tt) * g.nsb + z * g.nsb0 + j * g.tilew + i;
+    }
     const int sb = rem / g.tchunk, tt = rem - sb * g.tchunk;
     return (chunk * g.tchunk + tt) * g.nsb + sb;
 }
