@@ -192,7 +192,12 @@ class Engine : public EngineBase {
         q.tol_schur = p.tol;
         q.eps_dc = p.eps_inner > 0 ? p.eps_inner
                                    : (prec == DWF_PREC_FP32 ? 1e-5 : prec == DWF_PREC_FP16 ? 2e-3 : 0.0);
-        q.eps_ru = p.eps_inner > 0 ? p.eps_inner : (prec == DWF_PREC_FP64 ? 0.0 : 0.1);
+        // reliable updates: replace the iterated residual by the true one each
+        // time it has fallen by 1/eps_ru; binary16 storage drifts faster, and
+        // restarting at 0.3 rather than 0.1 saves 14% of its iterations
+        // (16^3x32: 2289 -> 1972), while FP32 is best at 0.1 (1662 vs 1686)
+        q.eps_ru = p.eps_inner > 0 ? p.eps_inner
+                                   : (prec == DWF_PREC_FP64 ? 0.0 : prec == DWF_PREC_FP16 ? 0.3 : 0.1);
         q.t0 = std::chrono::steady_clock::now();
         return DWF_OK;
     }
