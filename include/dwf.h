@@ -92,7 +92,11 @@ typedef struct dwf_solve_params {
     int inner_prec;          /* DWF_PREC_FP32 (default), DWF_PREC_FP16 or DWF_PREC_FP64   */
     int reliable;            /* 1: reliable updates, falling back to defect correction
                                 when they stall (default); 0: defect correction only     */
-    double eps_inner;        /* inner relative tolerance; 0 = per-precision default       */
+    double eps_inner;        /* inner relative tolerance of a cycle; 0 = per-precision
+                                default: reliable updates restart when the iterated residual
+                                has fallen to 0.1 (FP32) / 0.3 (FP16 storage) of its value
+                                at the last restart; defect correction cycles run to 1e-5
+                                (FP32) / 2e-3 (FP16); FP64 inner solves run to tol        */
     int maxiter;             /* cap on inner iterations per right-hand side (default 50000) */
     int check_every;         /* inner iterations between host checks; 0 = adaptive        */
     int use_graph;           /* 1: capture inner iterations in a hipGraph (default)       */

@@ -193,7 +193,8 @@ class Engine : public EngineBase {
         q.eps_dc = p.eps_inner > 0 ? p.eps_inner
                                    : (prec == DWF_PREC_FP32 ? 1e-5 : prec == DWF_PREC_FP16 ? 2e-3 : 0.0);
         // reliable updates: replace the iterated residual by the true one each
-        // time it has fallen by 1/eps_ru; binary16 storage drifts faster, and
+        // time it has fallen to eps_ru of its value at the last restart;
+        // binary16 storage drifts faster, and
         // restarting at 0.3 rather than 0.1 saves 14% of its iterations
         // (16^3x32: 2289 -> 1972), while FP32 is best at 0.1 (1662 vs 1686)
         q.eps_ru = p.eps_inner > 0 ? p.eps_inner
