@@ -251,3 +251,31 @@ def test_gauge_covariance_on_gpu(prec):
     finally:
         c1.close()
         c2.close()
+
+
+# 24 x 24 z-planes (18 FP32 / 36 FP64 blocks of 16 / 8 sites) with 4 t-slices
+# per XCD chunk: the launches walk the planes in tiles (the order used at
+# 24^3 x 48), which every other operator test here leaves untouched
+_rng_t = np.random.default_rng(81)
+TILED = Problem((24, 24, 2, 32), 16, 1.8, 0.02, *(2 * [_rng_t.uniform(0.5, 1.5, 16)]), 0.5, 43, 44)
+_TILED_EXP = {}
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+def test_tiled_block_order_parity(prec):
+    """Operators on a lattice whose z-planes are walked in tiles of workgroups
+    equal the oracle's: every block is visited exactly once in that order."""
+    import paper_1101_0423_amd as dwf
+    print(f"[ops] tiled block order prec={prec}", flush=True)
+    ops = [dwf.OP_DW, dwf.OP_HOP_EO, dwf.OP_HOP_OE, dwf.OP_M5, dwf.OP_C, dwf.OP_D]
+    c = TILED.context()
+    try:
+        for op in ops:
+            if op not in _TILED_EXP:
+                _TILED_EXP[op] = oracle_op(TILED, op, TILED.b)
+            got = c.apply(op, TILED.b, prec=prec)
+            exp = _TILED_EXP[op]
+            assert rel(got, exp) <= TOL[prec], (OP_NAMES[op], rel(got, exp))
+            assert max_rel(got, exp) <= 4 * TOL[prec], OP_NAMES[op]
+    finally:
+        c.close()
