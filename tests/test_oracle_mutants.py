@@ -48,6 +48,15 @@ MUTANTS = [
     ("force-solve CG accumulates r instead of p",
      "for (long i = 0; i < N; i++) { ww[i] += alpha * p[i]; r[i] -= alpha * ap[i]; }",
      "for (long i = 0; i < N; i++) { ww[i] += alpha * r[i]; r[i] -= alpha * ap[i]; }"),
+    ("true residual without the square root", "return n > 0 ? sqrt(r / n) : sqrt(r);",
+     "return n > 0 ? (r / n) : sqrt(r);"),
+    ("true residual relative to |D x| instead of |b|", "double r = norm2(N, dx), n = norm2(N, bb);",
+     "double r = norm2(N, dx), n = norm2(N, bb) + r;"),
+    ("initial guess read through S2 instead of S2^-1", "apply_s(&S.l, Ns, S2ip, S2im, xx, y);",
+     "apply_s(&S.l, Ns, S2p, S2m, xx, y);"),
+    ("CGNE direction update without beta (steepest descent)",
+     "for (long i = 0; i < N; i++) p[i] = r[i] + beta * p[i];\n        rr = rr_new;\n        k++;\n    }\n    *iters = k;\n    *relres = bb",
+     "for (long i = 0; i < N; i++) p[i] = r[i] + 0.0 * beta * p[i];\n        rr = rr_new;\n        k++;\n    }\n    *iters = k;\n    *relres = bb"),
 ]
 
 

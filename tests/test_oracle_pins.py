@@ -330,6 +330,104 @@ def test_schur_complement_definition():
 
 
 # ---------------------------------------------------------------------------
+# the true residual, the initial-guess path of the solve, truncated CG
+# ---------------------------------------------------------------------------
+
+
+def _dense_problem(kind, seed=31):
+    dims, ns, m0, mq = (2, 2, 2, 2), 4, 1.8, 0.05
+    U = inp.gauge_field(dims, 0.3, seed=seed)
+    sigma, omega = weights(kind, ns)
+    a = (U, dims, ns, m0, mq, sigma, omega)
+    shape = (2, 2, 2, 2, ns, 24)
+    D = dense_matrix(lambda v: oracle.d5(*a, v), shape)
+    b = rnd(dims, ns, seed + 1)
+    xd = np.linalg.solve(D, inp.host_to_complex(b).ravel())
+    xs = inp.complex_to_host(xd.reshape(shape[:-1] + (12,)))
+    return a, shape, b, xs
+
+
+@pytest.mark.parametrize("kind", ["shamir", "general"])
+def test_truncated_cg_iterates_minimise_the_error(kind):
+    """After k iterations from zero, CG on C C^dag w = b'' tracking y = C^dag w
+    (Craig's method) holds the y of the Krylov space
+    span{C^dag (C C^dag)^j b'', j < k} closest to y* = C^-1 b'': checked by
+    projecting y* (from a dense LAPACK solve) onto that space.  The oracle's
+    solve capped at k iterations is then the reconstruction of that y, which is
+    compared through its Schur part y_o = (S2^-1 x)_o."""
+    a, shape, b, xs = _dense_problem(kind, seed=43)
+    U, dims, ns = a[0], a[1], a[2]
+    Xp, Xm, Yp, Ym = oracle.xy(*a[2:])
+    sw = np.diag(np.sqrt(a[6]))
+    s2i = [np.linalg.inv(sw) @ Y for Y in (Yp, Ym)]          # S2^-1 = sqrt(w)^-1 Y
+
+    def schur_part(x):
+        return inp.host_to_complex(on_parity(oracle.apply_s(dims, ns, *s2i, x), dims, 1)).ravel()
+
+    C = dense_matrix(lambda v: oracle.schur_c(*a, on_parity(v, dims, 1)), shape)
+    odd = np.repeat(parity_mask(dims).ravel() == 1, ns * 12)
+    Co = C[np.ix_(odd, odd)]
+    ystar = schur_part(xs)[odd]
+    bpp = Co @ ystar                                        # b'' = C y*
+    kry, v = [], bpp.copy()
+    for k in range(1, 6):
+        kry.append(Co.conj().T @ v)
+        v = Co @ kry[-1]
+        Q, _ = np.linalg.qr(np.array(kry).T)
+        yk = Q @ (Q.conj().T @ ystar)                       # orthogonal projection of y*
+        x, info = oracle.solve(*a, b, tol=1e-300, maxiter=k)
+        assert info["iters"] == k and not info["converged"]
+        got = schur_part(x)[odd]
+        assert np.linalg.norm(got - yk) <= 1e-11 * np.linalg.norm(yk), k
+
+
+@pytest.mark.parametrize("kind", ["shamir", "general"])
+def test_true_residual_closed_forms(kind):
+    """|b - D x| / |b| on points where its value is known without the oracle's
+    formula: x = 0 gives exactly 1; x = t x* with x* the LAPACK solution of
+    D x = b gives |1 - t| (b - D t x* = (1 - t) b); x* itself gives rounding;
+    b = 0 and x = 0 give 0."""
+    a, shape, b, xs = _dense_problem(kind)
+    assert oracle.true_residual(*a, b, np.zeros_like(b)) == 1.0
+    for t in (0.5, 0.9, 1.25, -2.0):
+        r = oracle.true_residual(*a, b, t * xs)
+        assert abs(r - abs(1 - t)) <= 1e-13 * max(1.0, abs(1 - t)), (t, r)
+    assert oracle.true_residual(*a, b, xs) < 1e-13
+    assert oracle.true_residual(*a, np.zeros_like(b), np.zeros_like(b)) == 0.0
+    # a residual confined to one site and slice: b = D x + e gives |e| / |b|
+    e = np.zeros_like(b)
+    e[1, 0, 1, 1, 2, 5] = 0.25
+    r = oracle.true_residual(*a, b + e, xs)
+    assert abs(r - 0.25 / np.linalg.norm(b + e)) <= 1e-12 * r
+
+
+@pytest.mark.parametrize("kind", ["shamir", "general"])
+def test_solve_initial_guess_path(kind):
+    """The solve's initial guess enters through y_o = (S2^-1 x)_o: the LAPACK
+    solution as the guess is already converged (no CG iteration, returned as
+    is up to rounding), and a guess that differs from it only on even sites
+    still needs none (the even half is rebuilt from y_o by Eq. (10))."""
+    a, shape, b, xs = _dense_problem(kind, seed=37)
+    x, info = oracle.solve(*a, b, tol=1e-10, x0=xs)
+    assert info["converged"] and info["iters"] == 0, info
+    assert rel(x, xs) < 1e-12
+    # S2 y changes both parities; the guess is read only through (S2^-1 x0)_o,
+    # so add to x* something whose image under S2^-1 vanishes on odd sites
+    Xp, Xm, Yp, Ym = oracle.xy(a[2], a[3], a[4], a[5], a[6])
+    sw = np.diag(np.sqrt(a[6]))
+    s2 = [np.linalg.inv(Y) @ sw for Y in (Yp, Ym)]
+    junk = on_parity(rnd(a[1], a[2], 41), a[1], 0)
+    x0 = xs + oracle.apply_s(a[1], a[2], *s2, junk)
+    x, info = oracle.solve(*a, b, tol=1e-10, x0=x0)
+    assert info["converged"] and info["iters"] == 0, info
+    assert rel(x, xs) < 1e-12
+    # a guess away from x* takes iterations and still converges
+    x, info = oracle.solve(*a, b, tol=1e-12, x0=0.5 * xs)
+    assert info["converged"] and info["iters"] > 0
+    assert rel(x, xs) < 1e-10
+
+
+# ---------------------------------------------------------------------------
 # brute force: dense LAPACK solve on a 2^4 x Ns = 4 lattice
 # ---------------------------------------------------------------------------
 
