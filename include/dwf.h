@@ -76,6 +76,25 @@ extern "C" {
 #define DWF_PREC_FP32 1
 #define DWF_PREC_FP16 2  /* binary16 storage with one FP32 scale per 5D site, FP32 arithmetic */
 
+/* Gauge-link storage of a dwf_apply, or-ed into its prec argument (Sec. 3.2
+ * stages the links of a site once for all Ns slices; the paper gives no
+ * storage format):
+ *   DWF_LINKS_AUTO : the inner solver's choice -- FP64 18 reals; FP32 and
+ *                    FP16 storage 12 reals (rows 0 and 1, row 2 rebuilt as
+ *                    conj(row0 x row1)) when the field passes the SU(3) check
+ *                    of dwf_create, else 18 reals (FP32)
+ *   DWF_LINKS_18   : all 18 reals (FP64, FP32)
+ *   DWF_LINKS_12   : 12 reals (FP32, FP16); DWF_EINVAL unless the field is SU(3)
+ * Other combinations give DWF_EINVAL. */
+#define DWF_LINKS_AUTO 0x000
+#define DWF_LINKS_18 0x100
+#define DWF_LINKS_12 0x200
+
+/* A field is SU(3) for the 12-real links when every link satisfies
+ * max_b |U_2b - conj(U_0 x U_1)_b| <= DWF_SU3_TOL (the FP32 rounding scale):
+ * then the third row rebuilt from the first two is the stored one. */
+#define DWF_SU3_TOL 1e-6
+
 typedef struct dwf_ctx dwf_ctx;
 
 typedef struct dwf_opts {
@@ -101,8 +120,11 @@ typedef struct dwf_solve_params {
     int check_every;         /* inner iterations between host checks; 0 = adaptive        */
     int use_graph;           /* 1: capture inner iterations in a hipGraph (default)       */
     int link_compress;       /* links in the inner solve: -1 auto (default: 12-real rows 0-1,
-                                row 2 = conj(row0 x row1), for FP32 and FP16 storage);
-                                0: 18-real (FP32); 1: 12-real.  FP64 always uses 18-real   */
+                                row 2 = conj(row0 x row1), for FP32 and FP16 storage when
+                                the field passes the SU(3) check of dwf_create, else 18-real);
+                                0: 18-real (FP32); 1: 12-real (DWF_EINVAL for a field that
+                                is not SU(3)).  FP64 always uses 18-real; FP16 storage needs
+                                an SU(3) field (DWF_EINVAL otherwise)                      */
     int use_guess;           /* 1: x holds an initial guess on entry; 0: start from zero  */
     int debug_stall_after;   /* test hook: >0 declares reliable updates stalled after this
                                 many restarts, forcing the defect-correction fallback     */
@@ -153,9 +175,24 @@ int dwf_create(dwf_ctx **out, const double *gauge, const int dims[4], int Ns,
 void dwf_destroy(dwf_ctx *ctx);
 
 /*
+ * dwf_gauge_su3_deviation -- host-only check behind the 12-real link storage:
+ * *dev = max over links and columns b of |U_2b - conj(U_0 x U_1)_b| (the
+ * difference between the third row and the one the 12-real storage rebuilds
+ * from the first two; +inf if any entry is not finite).  gauge and dims as in
+ * dwf_create.  dwf_create runs the same check; a field above DWF_SU3_TOL is
+ * solved with 18-real links in FP32, and 12-real links or FP16 storage are
+ * refused for it (DWF_EINVAL).  Touches no device.
+ */
+int dwf_gauge_su3_deviation(const double *gauge, const int dims[4], double *dev);
+
+/*
  * dwf_apply -- out = op(in) for nrhs spinors in the host layout, in
- * precision prec (inputs are rounded to prec, outputs returned in FP64).
- * in, out: host pointers of nrhs * V4 * Ns * 24 doubles.
+ * precision prec (inputs are rounded to prec, outputs returned in FP64),
+ * optionally or-ed with a DWF_LINKS_* link storage.
+ * in, out: host pointers of nrhs * V4 * Ns * 24 doubles.  The host forms
+ * stage one spinor at a time through a device buffer that the context keeps
+ * (allocated at the first host-pointer call, two spinors), so they allocate
+ * no device memory per call.
  */
 int dwf_apply(dwf_ctx *ctx, int op, int prec, const double *in, double *out, int nrhs);
 
@@ -173,7 +210,9 @@ int dwf_apply_dev(dwf_ctx *ctx, int op, int prec, const double *in_dev, double *
  * With nrhs > 1 the right-hand sides are solved together through the
  * multi-RHS stencil (each gauge link is read once for all of them).
  * Returns DWF_OK when every right-hand side reached params->tol, else
- * DWF_ENOCONV.
+ * DWF_ENOCONV.  Like dwf_apply, the host form stages one spinor at a time
+ * through the context's device buffer (no device allocation per call; the
+ * solve engine itself is allocated once per (params, nrhs) and kept).
  */
 int dwf_solve(dwf_ctx *ctx, const double *b, double *x, int nrhs,
               const dwf_solve_params *params, dwf_solve_stats *stats);
@@ -226,6 +265,18 @@ int dwf_server_stats_get(dwf_server_stats *out, int reset);
  */
 int dwf_time_kernels(dwf_ctx *ctx, const dwf_solve_params *params, int nrhs, int launches,
                      double ms[5], double bytes[5]);
+
+/*
+ * dwf_stream_copy -- profiling aid: a plain copy of bytes (a multiple of 16)
+ * from src_dev to dst_dev on device `device` and the given HIP stream (not
+ * NULL), with ordinary cached loads and stores (nontemporal = 0, as the hop
+ * kernels gather their inputs) or non-temporal ones (1, as the CG kernels
+ * stream vectors they touch once).  Its known byte count calibrates the
+ * memory counters that measure the other kernels' traffic.  Returns after
+ * the copy has finished.
+ */
+int dwf_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, int nontemporal, int device,
+                    void *hip_stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *dwf_last_error(void);

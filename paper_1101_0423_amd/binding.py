@@ -18,12 +18,16 @@ DWF_OK, DWF_PENDING = 0, 1
 DWF_EINVAL, DWF_ENOMEM, DWF_EDEVICE, DWF_ENOCONV, DWF_EBUSY, DWF_ENOTFOUND = -1, -2, -3, -4, -5, -6
 (OP_DW, OP_HOP_EO, OP_HOP_OE, OP_M5, OP_M5T, OP_C, OP_CDAG, OP_CCDAG, OP_D, OP_DDAG) = range(10)
 PREC_FP64, PREC_FP32, PREC_FP16 = 0, 1, 2
+# gauge-link storage of dwf_apply, or-ed into prec
+LINKS_AUTO, LINKS_18, LINKS_12 = 0x000, 0x100, 0x200
+SU3_TOL = 1e-6
 
 # every function declared in include/dwf.h
 EXPORTED = [
     "dwf_default_opts", "dwf_default_params", "dwf_create", "dwf_destroy", "dwf_apply", "dwf_apply_dev",
     "dwf_solve", "dwf_solve_dev", "dwf_submit", "dwf_submit_mass", "dwf_poll", "dwf_server_stats_get",
-    "dwf_time_kernels", "dwf_last_error", "dwf_version",
+    "dwf_time_kernels", "dwf_last_error", "dwf_version", "dwf_gauge_su3_deviation",
+    "dwf_stream_copy",
 ]
 
 
@@ -111,6 +115,8 @@ def lib():
     L.dwf_poll.argtypes = [ctypes.c_uint64, _dp, ctypes.POINTER(SolveStats), ctypes.c_int]
     L.dwf_server_stats_get.argtypes = [ctypes.POINTER(ServerStats), ctypes.c_int]
     L.dwf_time_kernels.argtypes = [vp, ctypes.POINTER(SolveParams), ctypes.c_int, ctypes.c_int, _dp, _dp]
+    L.dwf_gauge_su3_deviation.argtypes = [_dp, ctypes.POINTER(ctypes.c_int), _dp]
+    L.dwf_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp]
     L.dwf_last_error.restype = ctypes.c_char_p
     L.dwf_version.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -132,6 +138,60 @@ def _check(rc, ok=(DWF_OK,)):
 def _f64(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a
+
+
+def gauge_shape(dims):
+    lx, ly, lz, lt = (int(d) for d in dims)
+    return (lt, lz, ly, lx, 4, 3, 3, 2)
+
+
+def spinor_shape(dims, ns, nrhs=None):
+    lx, ly, lz, lt = (int(d) for d in dims)
+    s = (lt, lz, ly, lx, int(ns), 24)
+    return s if nrhs is None else (int(nrhs),) + s
+
+
+def check_host_spinors(a, dims, ns):
+    """A host array of one spinor [Lt][Lz][Ly][Lx][Ns][24] or nrhs of them
+    [nrhs][...]; returns it as contiguous float64 and nrhs.  Raises ValueError
+    on any other shape (the C side would read or write past its end)."""
+    a = _f64(a)
+    one = spinor_shape(dims, ns)
+    if a.shape == one:
+        return a, 1
+    if a.ndim == 7 and a.shape[1:] == one and a.shape[0] >= 1:
+        return a, a.shape[0]
+    raise ValueError(f"spinor array of shape {a.shape}; expected {one} or (nrhs,) + {one}")
+
+
+def check_device_spinors(t, dims, ns, nrhs, device):
+    """A torch tensor handed to a device-pointer entry point: float64, on the
+    context's GPU, contiguous and of exactly nrhs spinors.  Raises ValueError
+    otherwise (the kernels would read or write out of bounds)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("expected a torch tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"tensor dtype {t.dtype}; expected torch.float64")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"tensor on {t.device}; expected cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError("tensor is not contiguous")
+    n = int(nrhs) * int(np.prod(spinor_shape(dims, ns)))
+    if int(nrhs) < 1 or t.numel() != n:
+        raise ValueError(f"tensor of {t.numel()} elements; expected nrhs * V4 * Ns * 24 = {n}")
+    return t
+
+
+def gauge_su3_deviation(gauge, dims):
+    """max |U_2b - conj(U_0 x U_1)_b| over the field (dwf_gauge_su3_deviation)."""
+    g = _f64(gauge)
+    if g.shape != gauge_shape(dims):
+        raise ValueError(f"gauge array of shape {g.shape}; expected {gauge_shape(dims)}")
+    d = (ctypes.c_int * 4)(*[int(x) for x in dims])
+    out = ctypes.c_double()
+    _check(lib().dwf_gauge_su3_deviation(g.ctypes.data_as(_dp), d, ctypes.byref(out)))
+    return out.value
 
 
 def _ptr(a):
@@ -169,10 +229,15 @@ class Context:
         o.sites_per_block = sites_per_block
         o.xcd_remap = xcd_remap
         o.hbm_budget_bytes = hbm_budget_bytes
-        self.gauge = _f64(gauge)
         self.dims = tuple(int(d) for d in dims)
+        self.gauge = _f64(gauge)
+        if self.gauge.shape != gauge_shape(self.dims):
+            raise ValueError(f"gauge array of shape {self.gauge.shape}; expected {gauge_shape(self.dims)}")
+        self.device = int(device)
         self.ns, self.m0, self.mq = int(ns), float(m0), float(mq)
         self.sigma, self.omega = _f64(sigma), _f64(omega)
+        if self.sigma.shape != (self.ns,) or self.omega.shape != (self.ns,):
+            raise ValueError(f"sigma and omega must hold Ns = {self.ns} values")
         d = (ctypes.c_int * 4)(*self.dims)
         _check(L.dwf_create(ctypes.byref(self._h), _ptr(self.gauge), d, self.ns, self.m0, self.mq,
                             _ptr(self.sigma), _ptr(self.omega), ctypes.byref(o)))
@@ -182,9 +247,7 @@ class Context:
         return self._h
 
     def spinor_shape(self, nrhs=None):
-        lx, ly, lz, lt = self.dims
-        s = (lt, lz, ly, lx, self.ns, 24)
-        return s if nrhs is None else (nrhs,) + s
+        return spinor_shape(self.dims, self.ns, nrhs)
 
     def close(self):
         if self._h:
@@ -205,15 +268,17 @@ class Context:
 
     # -- operators -------------------------------------------------------
     def apply(self, op, psi, prec=PREC_FP64):
-        """out = op(psi) for host arrays [nrhs?][Lt][Lz][Ly][Lx][Ns][24]."""
-        psi = _f64(psi)
-        nrhs = 1 if psi.ndim == 6 else psi.shape[0]
+        """out = op(psi) for host arrays [nrhs?][Lt][Lz][Ly][Lx][Ns][24];
+        prec may carry a LINKS_* link storage."""
+        psi, nrhs = check_host_spinors(psi, self.dims, self.ns)
         out = np.empty_like(psi)
         _check(lib().dwf_apply(self._h, op, prec, _ptr(psi), _ptr(out), nrhs))
         return out
 
     def apply_dev(self, op, psi, out, prec=PREC_FP64, nrhs=1, stream=None):
         """Device tensors (torch float64, contiguous, host layout)."""
+        check_device_spinors(psi, self.dims, self.ns, nrhs, self.device)
+        check_device_spinors(out, self.dims, self.ns, nrhs, self.device)
         _check(lib().dwf_apply_dev(self._h, op, prec, ctypes.c_void_p(psi.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), nrhs, _stream_ptr(stream)))
         return out
@@ -221,11 +286,12 @@ class Context:
     # -- solves ----------------------------------------------------------
     def solve(self, b, x0=None, params=None, **kw):
         """Solve D x = b for host arrays; returns (x, [stats dict per rhs], status)."""
-        b = _f64(b)
-        nrhs = 1 if b.ndim == 6 else b.shape[0]
+        b, nrhs = check_host_spinors(b, self.dims, self.ns)
         p = params if params is not None else default_params(**kw)
         if x0 is not None:
             x = _f64(x0).copy()
+            if x.shape != b.shape:
+                raise ValueError(f"guess of shape {x.shape}; expected {b.shape}")
             p.use_guess = 1
         else:
             x = np.zeros_like(b)
@@ -236,6 +302,8 @@ class Context:
 
     def solve_dev(self, b, x, nrhs=1, params=None, stream=None, **kw):
         p = params if params is not None else default_params(**kw)
+        check_device_spinors(b, self.dims, self.ns, nrhs, self.device)
+        check_device_spinors(x, self.dims, self.ns, nrhs, self.device)
         st = (SolveStats * nrhs)()
         rc = _check(lib().dwf_solve_dev(self._h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                         nrhs, ctypes.byref(p), st, _stream_ptr(stream)),
@@ -253,6 +321,8 @@ class Context:
     # -- serving ---------------------------------------------------------
     def submit(self, b, mq=None, params=None, **kw):
         b = _f64(b)
+        if b.shape != self.spinor_shape():
+            raise ValueError(f"spinor array of shape {b.shape}; expected {self.spinor_shape()}")
         p = params if params is not None else default_params(**kw)
         t = ctypes.c_uint64()
         if mq is None:
@@ -272,6 +342,19 @@ def poll(ticket, shape, timeout_us=0):
     if rc not in (DWF_OK, DWF_ENOCONV):
         raise DwfError(rc, last_error())
     return rc, x, st.as_dict()
+
+
+def stream_copy(src, dst, nontemporal=False, stream=None):
+    """Plain device copy src -> dst (torch tensors of equal byte size, a
+    multiple of 16) with cached or non-temporal accesses (dwf_stream_copy):
+    the calibration reference of the memory counters."""
+    nb = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("contiguous device tensors expected")
+    if dst.numel() * dst.element_size() != nb or nb % 16:
+        raise ValueError("equal sizes, a multiple of 16 bytes, expected")
+    _check(lib().dwf_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nb,
+                                 int(bool(nontemporal)), src.device.index, _stream_ptr(stream)))
 
 
 def server_stats(reset=False):

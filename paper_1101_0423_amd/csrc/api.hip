@@ -171,6 +171,17 @@ const TableSet* dwf_ctx::table_set(double mq_val, int* rc) {
     return raw;
 }
 
+int dwf_ctx::ensure_stage(double** in, double** out) {
+    const size_t n = (size_t)spinor_elems() * sizeof(double);
+    if (stage.bytes < 2 * n) {
+        int rc = stage.alloc(2 * n);
+        if (rc) return rc;
+    }
+    *in = stage.as<double>();
+    *out = stage.as<double>() + spinor_elems();
+    return DWF_OK;
+}
+
 int dwf_ctx::ensure_partials(size_t n) {
     size_t need = n * sizeof(double);
     if (partials_bytes >= need) return DWF_OK;
@@ -179,6 +190,55 @@ int dwf_ctx::ensure_partials(size_t n) {
     partials_bytes = need;
     return DWF_OK;
 }
+
+namespace dwf {
+
+double su3_deviation(const double* g, long nlinks) {
+    double dev = 0;
+    for (long l = 0; l < nlinks; ++l) {
+        const double* u = g + 18 * l;
+        // entry (a, b) = u[2 (3 a + b)] + i u[2 (3 a + b) + 1]
+        for (int b = 0; b < 3; ++b) {
+            const int b1 = (b + 1) % 3, b2 = (b + 2) % 3;
+            const double ar = u[2 * b1], ai = u[2 * b1 + 1], br = u[2 * (3 + b2)], bi = u[2 * (3 + b2) + 1];
+            const double cr = u[2 * b2], ci = u[2 * b2 + 1], dr = u[2 * (3 + b1)], di = u[2 * (3 + b1) + 1];
+            // (row0 x row1)_b = row0_{b1} row1_{b2} - row0_{b2} row1_{b1}; row 2 should be its conjugate
+            const double xr = (ar * br - ai * bi) - (cr * dr - ci * di);
+            const double xi = (ar * bi + ai * br) - (cr * di + ci * dr);
+            const double er = u[2 * (6 + b)] - xr, ei = u[2 * (6 + b) + 1] + xi;
+            const double d = sqrt(er * er + ei * ei);
+            if (!(d <= dev)) dev = std::isfinite(d) ? d : INFINITY;
+        }
+    }
+    return dev;
+}
+
+int link_format(const dwf_ctx* c, const dwf_solve_params& p) {
+    switch (p.inner_prec) {
+        case DWF_PREC_FP64: return LINK_D18;
+        case DWF_PREC_FP32:
+            if (p.link_compress == 1 || (p.link_compress == -1 && c->su3)) return LINK_S12;
+            return LINK_S18;
+        default: return LINK_H12;
+    }
+}
+
+int check_params(const dwf_ctx* c, const dwf_solve_params& p) {
+    if (!(p.tol > 0)) return fail(DWF_EINVAL, "tol must be > 0");
+    if (p.inner_prec < DWF_PREC_FP64 || p.inner_prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "bad inner_prec");
+    if (p.maxiter < 1) return fail(DWF_EINVAL, "maxiter must be >= 1");
+    if (p.link_compress < -1 || p.link_compress > 1) return fail(DWF_EINVAL, "link_compress must be -1, 0 or 1");
+    if (p.system != DWF_SYSTEM_D && p.system != DWF_SYSTEM_CCDAG) return fail(DWF_EINVAL, "unknown system");
+    if (!c->su3 && p.inner_prec == DWF_PREC_FP32 && p.link_compress == 1)
+        return fail(DWF_EINVAL, "12-real links need an SU(3) field (row 2 = conj(row 0 x row 1)); this field "
+                                "deviates by " + std::to_string(c->su3_dev));
+    if (!c->su3 && p.inner_prec == DWF_PREC_FP16)
+        return fail(DWF_EINVAL, "FP16 storage uses 12-real links, which need an SU(3) field; this field deviates by " +
+                                    std::to_string(c->su3_dev));
+    return DWF_OK;
+}
+
+}  // namespace dwf
 
 namespace {
 
@@ -229,6 +289,16 @@ void dwf_default_params(dwf_solve_params* p) {
 
 const char* dwf_last_error(void) { return g_err.c_str(); }
 
+int dwf_gauge_su3_deviation(const double* gauge, const int dims[4], double* dev) {
+    g_err.clear();
+    if (!gauge || !dims || !dev) return fail(DWF_EINVAL, "NULL gauge, dims or dev");
+    for (int i = 0; i < 4; ++i)
+        if (dims[i] < 2 || dims[i] % 2) return fail(DWF_EINVAL, "every lattice extent must be even and >= 2");
+    const long V4 = (long)dims[0] * dims[1] * dims[2] * dims[3];
+    *dev = su3_deviation(gauge, V4 * 4);
+    return DWF_OK;
+}
+
 const char* dwf_version(void) { return "libdwf 0.1 (gfx950)"; }
 
 int dwf_create(dwf_ctx** out, const double* gauge, const int dims[4], int Ns, double m0, double mq,
@@ -268,6 +338,11 @@ int dwf_create(dwf_ctx** out, const double* gauge, const int dims[4], int Ns, do
     c->V4 = V4;
     c->V4h = V4 / 2;
     c->V5h = c->V4h * Ns;
+    // 12-real links rebuild row 2 from rows 0 and 1: exact only for SU(3)
+    // fields (a U(3) field, or one with phases folded into its links, is
+    // solved with 18-real links)
+    c->su3_dev = su3_deviation(gauge, V4 * 4);
+    c->su3 = c->su3_dev <= DWF_SU3_TOL;
     // workgroups of G 4D sites x Ns slices, at most 256 lanes
     int G = c->opts.sites_per_block;
     if (G < 0 || G * Ns > 256) return fail(DWF_EINVAL, "sites_per_block * Ns must be <= 256");
@@ -331,7 +406,15 @@ namespace {
 int check_apply(dwf_ctx* c, int op, int prec, const void* in, const void* out, int nrhs) {
     if (!c || !in || !out) return fail(DWF_EINVAL, "NULL context or buffer");
     if (op < DWF_OP_DW || op > DWF_OP_DDAG) return fail(DWF_EINVAL, "unknown operator");
-    if (prec < DWF_PREC_FP64 || prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "unknown precision");
+    const int pr = prec & 0xff, lk = prec & ~0xff;
+    if (pr < DWF_PREC_FP64 || pr > DWF_PREC_FP16) return fail(DWF_EINVAL, "unknown precision");
+    if (lk != DWF_LINKS_AUTO && lk != DWF_LINKS_18 && lk != DWF_LINKS_12)
+        return fail(DWF_EINVAL, "unknown link storage");
+    if (pr == DWF_PREC_FP64 && lk == DWF_LINKS_12) return fail(DWF_EINVAL, "FP64 uses 18-real links");
+    if (pr == DWF_PREC_FP16 && lk == DWF_LINKS_18) return fail(DWF_EINVAL, "FP16 storage uses 12-real links");
+    if (!c->su3 && (lk == DWF_LINKS_12 || pr == DWF_PREC_FP16))
+        return fail(DWF_EINVAL, "12-real links need an SU(3) field; this field deviates by " +
+                                    std::to_string(c->su3_dev));
     if (nrhs < 1) return fail(DWF_EINVAL, "nrhs must be >= 1");
     return DWF_OK;
 }
@@ -344,12 +427,7 @@ int check_solve(dwf_ctx* c, const void* b, const void* x, int nrhs, const dwf_so
         *p = *params;
     else
         dwf_default_params(p);
-    if (!(p->tol > 0)) return fail(DWF_EINVAL, "tol must be > 0");
-    if (p->inner_prec < DWF_PREC_FP64 || p->inner_prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "bad inner_prec");
-    if (p->maxiter < 1) return fail(DWF_EINVAL, "maxiter must be >= 1");
-    if (p->link_compress < -1 || p->link_compress > 1) return fail(DWF_EINVAL, "link_compress must be -1, 0 or 1");
-    if (p->system != DWF_SYSTEM_D && p->system != DWF_SYSTEM_CCDAG) return fail(DWF_EINVAL, "unknown system");
-    return DWF_OK;
+    return check_params(c, *p);
 }
 
 }  // namespace
@@ -368,23 +446,18 @@ int dwf_apply_dev(dwf_ctx* c, int op, int prec, const double* in_dev, double* ou
     return DWF_OK;
 }
 
-// The host-pointer forms copy on the context's stream (never the legacy
-// stream, which would conflict with the request server's graph captures).
+// The host-pointer forms stage one spinor at a time through the context's
+// two-spinor device buffer, on the context's stream (never the legacy stream,
+// which would conflict with the request server's graph captures).
 int dwf_apply(dwf_ctx* c, int op, int prec, const double* in, double* out, int nrhs) {
     g_err.clear();
     int rc = check_apply(c, op, prec, in, out, nrhs);
     if (rc) return rc;
-    const size_t n = (size_t)nrhs * c->V4 * c->Ns * 24 * sizeof(double);
     std::lock_guard<std::mutex> lk(c->mtx);
     DWF_HIP(hipSetDevice(c->device));
-    hipStream_t s = c->stream;
-    DevBuf din, dout;
-    if ((rc = din.alloc(n)) || (rc = dout.alloc(n))) return rc;
-    DWF_HIP(hipMemcpyAsync(din.p, in, n, hipMemcpyHostToDevice, s));
-    if ((rc = apply_op(c, op, prec, din.as<double>(), dout.as<double>(), nrhs, s))) return rc;
-    DWF_HIP(hipMemcpyAsync(out, dout.p, n, hipMemcpyDeviceToHost, s));
-    DWF_HIP(hipStreamSynchronize(s));
-    return DWF_OK;
+    HostIO io{in, out, nullptr, nullptr};
+    if ((rc = c->ensure_stage(&io.stage_in, &io.stage_out))) return rc;
+    return apply_op(c, op, prec, nullptr, nullptr, nrhs, c->stream, &io);
 }
 
 int dwf_solve_dev(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params* params,
@@ -414,27 +487,31 @@ int dwf_time_kernels(dwf_ctx* c, const dwf_solve_params* params, int nrhs, int l
     return time_inner_kernels(c, p, nrhs, launches, ms, bytes);
 }
 
+int dwf_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, int nontemporal, int device,
+                    void* stream) {
+    g_err.clear();
+    if (!src_dev || !dst_dev) return fail(DWF_EINVAL, "NULL buffer");
+    if (bytes % 16) return fail(DWF_EINVAL, "bytes must be a multiple of 16");
+    if (nontemporal != 0 && nontemporal != 1) return fail(DWF_EINVAL, "nontemporal must be 0 or 1");
+    DWF_HIP(hipSetDevice(device));
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return fail(DWF_EINVAL, "a stream is required");
+    DWF_HIP(stream_copy(src_dev, dst_dev, bytes, nontemporal != 0, s));
+    DWF_HIP(hipStreamSynchronize(s));
+    return DWF_OK;
+}
+
 int dwf_solve(dwf_ctx* c, const double* b, double* x, int nrhs, const dwf_solve_params* params,
               dwf_solve_stats* stats) {
     g_err.clear();
     dwf_solve_params p;
     int rc = check_solve(c, b, x, nrhs, params, &p);
     if (rc) return rc;
-    const size_t n = (size_t)nrhs * c->V4 * c->Ns * 24 * sizeof(double);
     std::lock_guard<std::mutex> lk(c->mtx);
     DWF_HIP(hipSetDevice(c->device));
-    hipStream_t s = c->stream;
-    DevBuf db, dx;
-    if ((rc = db.alloc(n)) || (rc = dx.alloc(n))) return rc;
-    DWF_HIP(hipMemcpyAsync(db.p, b, n, hipMemcpyHostToDevice, s));
-    if (p.use_guess) DWF_HIP(hipMemcpyAsync(dx.p, x, n, hipMemcpyHostToDevice, s));
-    rc = solve(c, db.as<double>(), dx.as<double>(), nrhs, p, stats, s);
-    if (rc != DWF_OK && rc != DWF_ENOCONV) return rc;
-    const std::string msg = dwf_last_error();
-    DWF_HIP(hipMemcpyAsync(x, dx.p, n, hipMemcpyDeviceToHost, s));
-    DWF_HIP(hipStreamSynchronize(s));
-    if (rc) fail(rc, msg);
-    return rc;
+    HostIO io{b, x, nullptr, nullptr};
+    if ((rc = c->ensure_stage(&io.stage_in, &io.stage_out))) return rc;
+    return solve(c, nullptr, nullptr, nrhs, p, stats, c->stream, &io);
 }
 
 }  // extern "C"

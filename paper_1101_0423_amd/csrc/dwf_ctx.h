@@ -152,7 +152,13 @@ class EngineBase {
 };
 
 int make_engine(dwf_ctx* c, const dwf_solve_params& p, int K, hipStream_t s, std::unique_ptr<EngineBase>* out);
-int link_format(const dwf_solve_params& p);
+// link format of an inner solve: the params' choice, with auto resolved by the
+// field's SU(3) check (12-real only for SU(3) fields)
+int link_format(const dwf_ctx* c, const dwf_solve_params& p);
+// rejects parameters that the field or the library cannot serve (DWF_EINVAL)
+int check_params(const dwf_ctx* c, const dwf_solve_params& p);
+// max over links of |row 2 - conj(row 0 x row 1)| (+inf for non-finite entries)
+double su3_deviation(const double* gauge, long nlinks);
 // device bytes of an engine with K slots (fields, tables, state, reductions)
 size_t engine_bytes(const dwf_ctx* c, int inner_prec, int K);
 
@@ -180,10 +186,16 @@ struct dwf_ctx {
     dwf::DevBuf partials;  // block sums
     size_t partials_bytes = 0;
     std::string gauge_key;
+    double su3_dev = 0;    // su3_deviation of the field
+    bool su3 = true;       // su3_dev <= DWF_SU3_TOL: 12-real links are exact
+    dwf::DevBuf stage;     // host-pointer forms: one spinor in, one out (FP64, host layout)
 
     dwf::Geom geom(int out_parity, bool fp64) const;
     const dwf::TableSet* table_set(double mq_val, int* rc);
     int ensure_partials(size_t nblocks_times_nrhs);
+    long spinor_elems() const { return V4 * Ns * 24; }
+    // the two staging spinors of the host-pointer forms (allocated once)
+    int ensure_stage(double** in, double** out);
 };
 
 namespace dwf {
@@ -280,13 +292,27 @@ hipError_t half_copy(const dwf_ctx* c, HalfField& dst, const HalfField& src, int
 hipError_t half_acc(const dwf_ctx* c, HalfField& yhat, const HalfField& y, int nrhs, const int* mask,
                     hipStream_t s);
 hipError_t pack_links(const dwf_ctx* c, const double* gauge_dev, hipStream_t s);
+// plain copy of bytes (a multiple of 16), cached or non-temporal accesses
+hipError_t stream_copy(const void* src, void* dst, size_t bytes, bool nontemporal, hipStream_t s);
 
-// operator application on half fields (ops.hip)
-int apply_op(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs, hipStream_t s);
+// Host-pointer operands of apply_op / solve: the spinors are copied one at a
+// time through the context's staging buffers (stage_in, stage_out).
+struct HostIO {
+    const double* in;   // host, nrhs spinors
+    double* out;        // host, nrhs spinors
+    double* stage_in;   // device, one spinor
+    double* stage_out;  // device, one spinor
+};
 
-// the solver (solver.hip): nrhs right-hand sides, all with the context's mq
+// operator application on half fields (ops.hip).  prec may carry a DWF_LINKS_*
+// storage; in_dev / out_dev are device spinors unless hio is given.
+int apply_op(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs, hipStream_t s,
+             const HostIO* hio = nullptr);
+
+// the solver (solver.hip): nrhs right-hand sides, all with the context's mq;
+// b_dev / x_dev are device spinors unless hio is given (hio->in = b, hio->out = x)
 int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params& p,
-          dwf_solve_stats* stats, hipStream_t s);
+          dwf_solve_stats* stats, hipStream_t s, const HostIO* hio = nullptr);
 
 // the request server (server.hip): stop and forget the context's engines
 void server_detach(dwf_ctx* c);

@@ -231,7 +231,46 @@ __global__ void __launch_bounds__(kFinT) k_finish(const double* __restrict__ par
     }
 }
 
+// A plain copy of n 16-byte vectors, the calibration reference of the memory
+// counters: NT = 1 reads and writes with non-temporal (streaming) accesses as
+// the CG kernels do for vectors they touch once, NT = 0 with ordinary cached
+// accesses as for the gathered hop inputs.  Four vectors in flight per lane.
+template <bool NT>
+__global__ void __launch_bounds__(256) k_stream_copy(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                     long n) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += 4 * stride) {
+        f4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long j = i + k * stride;
+            if (j < n) v[k] = NT ? __builtin_nontemporal_load((const f4*)src + j) : ((const f4*)src)[j];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const long j = i + k * stride;
+            if (j < n) {
+                if (NT)
+                    __builtin_nontemporal_store(v[k], (f4*)dst + j);
+                else
+                    ((f4*)dst)[j] = v[k];
+            }
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t stream_copy(const void* src, void* dst, size_t bytes, bool nontemporal, hipStream_t s) {
+    const long n = (long)(bytes / 16);
+    const unsigned blocks = 4096;  // 16 waves per CU of 256
+    if (nontemporal)
+        hipLaunchKernelGGL(k_stream_copy<true>, dim3(blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n);
+    else
+        hipLaunchKernelGGL(k_stream_copy<false>, dim3(blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_finish(const double* partials, int nblocks, int nrhs, CgState st, int mode, hipStream_t s,
                          const int* mask) {

@@ -152,47 +152,85 @@ struct Applier {
     }
 };
 
+// The workspace of an application: NAPPLY half fields, kept by the context
+// per (precision, nrhs), or supplied by the caller (wsp).
 template <class Real, class F, class LF>
 int apply_impl(dwf_ctx* c, int op, int prec, LF e, LF o_, const double* in_dev, double* out_dev, int nrhs,
-               hipStream_t s) {
+               hipStream_t s, const HostIO* hio, Workspace* wsp = nullptr) {
     int rc;
-    const TableSet* ts = c->table_set(c->mq, &rc);
+    const TableSet* ts = c->table_set(c->mq, &rc);  // built by dwf_create for the context's mass
     if (!ts) return rc;
-    std::string key = "apply:" + std::to_string(prec) + ":" + std::to_string(nrhs);
-    auto& slot = c->ws[key];
-    if (!slot) {
-        slot.reset(new Workspace);
-        if ((rc = slot->alloc(std::vector<int>(NAPPLY, prec), c->V5h, c->Ns, nrhs))) {
-            slot.reset();
-            return rc;
+    Workspace* w = wsp;
+    if (!w) {
+        std::string key = "apply:" + std::to_string(prec) + ":" + std::to_string(nrhs);
+        auto& slot = c->ws[key];
+        if (!slot) {
+            slot.reset(new Workspace);
+            if ((rc = slot->alloc(std::vector<int>(NAPPLY, prec), c->V5h, c->Ns, nrhs))) {
+                slot.reset();
+                return rc;
+            }
         }
+        w = slot.get();
     }
-    Workspace* w = slot.get();
     Applier<Real, F, LF> A{c, ts, w, {e, o_}, KOpt{nullptr, nullptr, nrhs, 0}, s};
-    DWF_HIP(host_to_half(c, in_dev, nrhs, w->f(IN_E), w->f(IN_O), s));
+    const long n5 = c->spinor_elems();
+    if (hio) {
+        // one right-hand side at a time through the staging spinor; the
+        // conversion reading it is done before the next copy overwrites it
+        for (int r = 0; r < nrhs; ++r) {
+            DWF_HIP(hipMemcpyAsync(hio->stage_in, hio->in + r * n5, n5 * sizeof(double), hipMemcpyHostToDevice, s));
+            DWF_HIP(host_to_half(c, hio->stage_in, 1, w->f(IN_E), w->f(IN_O), s, r));
+            DWF_HIP(hipStreamSynchronize(s));
+        }
+    } else {
+        DWF_HIP(host_to_half(c, in_dev, nrhs, w->f(IN_E), w->f(IN_O), s));
+    }
     hipError_t err = A.run(op);
     if (err != hipSuccess) return fail(DWF_EDEVICE, std::string("operator kernels: ") + hipGetErrorString(err));
-    DWF_HIP(half_to_host(c, w->f(OUT_E), w->f(OUT_O), nrhs, out_dev, s));
+    if (hio) {
+        for (int r = 0; r < nrhs; ++r) {
+            DWF_HIP(half_to_host(c, w->f(OUT_E), w->f(OUT_O), 1, hio->stage_out, s, r));
+            DWF_HIP(hipMemcpyAsync(hio->out + r * n5, hio->stage_out, n5 * sizeof(double), hipMemcpyDeviceToHost, s));
+            DWF_HIP(hipStreamSynchronize(s));
+        }
+    } else {
+        DWF_HIP(half_to_host(c, w->f(OUT_E), w->f(OUT_O), nrhs, out_dev, s));
+    }
     return DWF_OK;
 }
 
-}  // namespace
-
-int apply_op(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs, hipStream_t s) {
+int dispatch(dwf_ctx* c, int op, int prec_flags, const double* in_dev, double* out_dev, int nrhs, hipStream_t s,
+             const HostIO* hio, Workspace* wsp) {
+    const int prec = prec_flags & 0xff, lk = prec_flags & ~0xff;
     switch (prec) {
         case DWF_PREC_FP64:
             return apply_impl<double, FD, LinkD18>(c, op, prec, LinkD18{c->links[0][LINK_D18].as<double>()},
                                                    LinkD18{c->links[1][LINK_D18].as<double>()}, in_dev, out_dev,
-                                                   nrhs, s);
+                                                   nrhs, s, hio, wsp);
         case DWF_PREC_FP32:
+            if (lk == DWF_LINKS_12 || (lk == DWF_LINKS_AUTO && c->su3))
+                return apply_impl<float, FS, LinkS12>(c, op, prec, LinkS12{c->links[0][LINK_S12].as<float>()},
+                                                      LinkS12{c->links[1][LINK_S12].as<float>()}, in_dev, out_dev,
+                                                      nrhs, s, hio, wsp);
             return apply_impl<float, FS, LinkS18>(c, op, prec, LinkS18{c->links[0][LINK_S18].as<float>()},
                                                   LinkS18{c->links[1][LINK_S18].as<float>()}, in_dev, out_dev,
-                                                  nrhs, s);
+                                                  nrhs, s, hio, wsp);
         default:
             return apply_impl<float, FH, LinkH12>(c, op, prec, LinkH12{c->links[0][LINK_H12].as<_Float16>()},
                                                   LinkH12{c->links[1][LINK_H12].as<_Float16>()}, in_dev, out_dev,
-                                                  nrhs, s);
+                                                  nrhs, s, hio, wsp);
     }
 }
+
+}  // namespace
+
+// prec: storage precision, or-ed with a DWF_LINKS_* link storage (validated by
+// the caller); auto picks what the inner solver uses for this field
+int apply_op(dwf_ctx* c, int op, int prec_flags, const double* in_dev, double* out_dev, int nrhs, hipStream_t s,
+             const HostIO* hio) {
+    return dispatch(c, op, prec_flags, in_dev, out_dev, nrhs, s, hio, nullptr);
+}
+
 
 }  // namespace dwf

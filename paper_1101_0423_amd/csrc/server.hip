@@ -61,7 +61,8 @@ struct Lane {
     std::vector<ReqP> slot;
     std::condition_variable cv;
     std::thread th;
-    bool cancel = false;  // fail everything and exit (context destroyed, shutdown)
+    bool cancel = false;   // fail everything and exit (context destroyed, shutdown)
+    bool closing = false;  // idle and giving its memory back: takes no new requests
     bool exited = false;
 };
 
@@ -94,7 +95,7 @@ size_t spinor_bytes_host(const dwf_ctx* c) { return (size_t)c->V4 * c->Ns * 24 *
 
 std::string lane_key(const dwf_ctx* c, const dwf_solve_params& p) {
     char buf[64];
-    snprintf(buf, sizeof(buf), "%p:%d:%d", (const void*)c, p.inner_prec, link_format(p));
+    snprintf(buf, sizeof(buf), "%p:%d:%d", (const void*)c, p.inner_prec, link_format(c, p));
     return buf;
 }
 
@@ -155,7 +156,9 @@ bool route(Server& S, const ReqP& q, bool front) {
     auto it = S.lanes.find(key);
     if (it != S.lanes.end()) {
         Lane* L = it->second.get();
-        if (L->cancel || L->exited) return false;
+        // a closing lane takes nothing more: the request waits and gets a new
+        // lane once this one has given its memory back
+        if (L->cancel || L->closing || L->exited) return false;
         L->queue.push_back(q);
         L->cv.notify_all();
         return true;
@@ -224,6 +227,7 @@ void lane_main(Lane* L) {
             while (!L->cancel && L->queue.empty() && eng->busy() == 0) {
                 if (!S.waiting.empty()) {  // memory is wanted elsewhere: release this lane
                     leave = true;
+                    L->closing = true;  // under the lock that found the queue empty
                     break;
                 }
                 L->cv.wait_for(lk, std::chrono::milliseconds(200));
@@ -366,14 +370,10 @@ int dwf_submit_mass(dwf_ctx* c, const double* b, double mq, const dwf_solve_para
         p = *params;
     else
         dwf_default_params(&p);
-    if (!(p.tol > 0)) return fail(DWF_EINVAL, "tol must be > 0");
-    if (p.inner_prec < DWF_PREC_FP64 || p.inner_prec > DWF_PREC_FP16) return fail(DWF_EINVAL, "bad inner_prec");
-    if (p.maxiter < 1) return fail(DWF_EINVAL, "maxiter must be >= 1");
-    if (p.link_compress < -1 || p.link_compress > 1) return fail(DWF_EINVAL, "link_compress must be -1, 0 or 1");
-    if (p.system != DWF_SYSTEM_D && p.system != DWF_SYSTEM_CCDAG) return fail(DWF_EINVAL, "unknown system");
+    int rc = check_params(c, p);
+    if (rc) return rc;
     p.use_guess = 0;
     DWF_HIP(hipSetDevice(c->device));
-    int rc;
     if (!c->table_set(mq, &rc)) return rc;  // rejects a singular (1 + cL) or X for this mass
     ReqP q(new Request);
     q->ctx = c;

@@ -58,14 +58,6 @@ double bytes_per_iter(const dwf_ctx* c, int inner_prec, int link_fmt) {
     return (double)c->V5h * (15.0 * sb + 2.0 * yb) + 4.0 * (double)c->V4h * 8.0 * link_bytes(link_fmt);
 }
 
-int link_format(const dwf_solve_params& p) {
-    switch (p.inner_prec) {
-        case DWF_PREC_FP64: return LINK_D18;
-        case DWF_PREC_FP32: return p.link_compress == 0 ? LINK_S18 : LINK_S12;  // auto: 12-real
-        default: return LINK_H12;
-    }
-}
-
 namespace {
 
 // half fields of an engine
@@ -985,8 +977,8 @@ int build(dwf_ctx* c, int prec, int fmt, int K, hipStream_t s, LF e, LF o, std::
     return DWF_OK;
 }
 
-std::string engine_key(const dwf_solve_params& p, int nrhs) {
-    return "solve:" + std::to_string(p.inner_prec) + ":" + std::to_string(link_format(p)) + ":" +
+std::string engine_key(const dwf_ctx* c, const dwf_solve_params& p, int nrhs) {
+    return "solve:" + std::to_string(p.inner_prec) + ":" + std::to_string(link_format(c, p)) + ":" +
            std::to_string(nrhs);
 }
 
@@ -999,7 +991,7 @@ int make_engine(dwf_ctx* c, const dwf_solve_params& p, int K, hipStream_t s, std
                                                   LinkD18{c->links[0][LINK_D18].as<double>()},
                                                   LinkD18{c->links[1][LINK_D18].as<double>()}, out);
         case DWF_PREC_FP32:
-            if (p.link_compress != 0)
+            if (link_format(c, p) == LINK_S12)
                 return build<float, FS, FS, LinkS12>(c, DWF_PREC_FP32, LINK_S12, K, s,
                                                      LinkS12{c->links[0][LINK_S12].as<float>()},
                                                      LinkS12{c->links[1][LINK_S12].as<float>()}, out);
@@ -1025,8 +1017,8 @@ size_t engine_bytes(const dwf_ctx* c, int prec, int K) {
 }
 
 int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params& p,
-          dwf_solve_stats* stats, hipStream_t s) {
-    const std::string key = engine_key(p, nrhs);
+          dwf_solve_stats* stats, hipStream_t s, const HostIO* hio) {
+    const std::string key = engine_key(c, p, nrhs);
     auto& slot = c->engines[key];
     if (!slot) {
         int rc = make_engine(c, p, nrhs, s, &slot);
@@ -1057,16 +1049,32 @@ int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_so
         return fail(rc, msg);
     };
     int rc;
-    for (int r = 0; r < nrhs; ++r)
-        if ((rc = eng->admit(r, b_dev + r * n5, p.use_guess ? x_dev + r * n5 : nullptr, c->mq, p)))
-            return abandon(rc);
+    for (int r = 0; r < nrhs; ++r) {
+        const double* b_r = hio ? hio->stage_in : b_dev + r * n5;
+        const double* x0_r = hio ? hio->stage_out : x_dev + r * n5;
+        if (hio) {  // one right-hand side (and guess) at a time through the staging spinors
+            if (hipMemcpyAsync(hio->stage_in, hio->in + r * n5, n5 * sizeof(double), hipMemcpyHostToDevice, s) !=
+                    hipSuccess ||
+                (p.use_guess && hipMemcpyAsync(hio->stage_out, hio->out + r * n5, n5 * sizeof(double),
+                                               hipMemcpyHostToDevice, s) != hipSuccess))
+                return abandon(fail(DWF_EDEVICE, "upload of b or the guess failed"));
+        }
+        if ((rc = eng->admit(r, b_r, p.use_guess ? x0_r : nullptr, c->mq, p))) return abandon(rc);
+        // the staging spinors are reused by the next right-hand side
+        if (hio && hipStreamSynchronize(s) != hipSuccess) return abandon(fail(DWF_EDEVICE, "admission failed"));
+    }
     // every tick either advances a slot's phase or runs inner iterations,
     // which end at the device-side iteration cap
     while (eng->pending() > 0)
         if ((rc = eng->tick())) return abandon(rc);
     std::vector<SlotResult> res(nrhs);
-    for (int r = 0; r < nrhs; ++r)
-        if ((rc = eng->retire(r, x_dev + r * n5, &res[r]))) return abandon(rc);
+    for (int r = 0; r < nrhs; ++r) {
+        if ((rc = eng->retire(r, hio ? hio->stage_out : x_dev + r * n5, &res[r]))) return abandon(rc);
+        if (hio && (hipMemcpyAsync(hio->out + r * n5, hio->stage_out, n5 * sizeof(double), hipMemcpyDeviceToHost,
+                                   s) != hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess))
+            return abandon(fail(DWF_EDEVICE, "download of x failed"));
+    }
     eng->report();
     DWF_HIP(hipEventRecord(ev1, s));
     DWF_HIP(hipEventSynchronize(ev1));
@@ -1102,7 +1110,7 @@ int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_so
 }
 
 int time_inner_kernels(dwf_ctx* c, const dwf_solve_params& p, int nrhs, int launches, double* ms, double* bytes) {
-    auto it = c->engines.find(engine_key(p, nrhs));
+    auto it = c->engines.find(engine_key(c, p, nrhs));
     if (it == c->engines.end() || !it->second)
         return fail(DWF_EINVAL, "no solve workspace for these parameters; run a solve first");
     it->second->set_stream(c->stream);

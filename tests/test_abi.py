@@ -146,3 +146,64 @@ def test_one_hip_runtime_per_process():
     libs = out.stdout.split()
     assert sum("libamdhip64" in p for p in libs) == 1, libs
     assert sum("libhsa-runtime64" in p for p in libs) == 1, libs
+
+
+def test_su3_deviation_check():
+    """The host-side check behind 12-real links: an SU(3) field passes; the same
+    field times a phase e^{i phi} (a U(3) field) deviates by
+    |1 - e^{-3 i phi}| max_b |U_2b| (row 2 picks up e^{i phi}, the conjugated
+    cross product of rows 0 and 1 e^{-2 i phi}); a non-finite entry gives inf."""
+    import dwf_inputs as inp
+    import paper_1101_0423_amd as dwf
+    dims = (4, 2, 2, 6)
+    U = inp.gauge_field(dims, 0.5, seed=3)
+    assert dwf.gauge_su3_deviation(U, dims) < 1e-14
+    phi = 0.013
+    z = (U[..., 0] + 1j * U[..., 1]) * np.exp(1j * phi)
+    Up = np.stack([z.real, z.imag], axis=-1)
+    dev = dwf.gauge_su3_deviation(Up, dims)
+    expect = abs(1 - np.exp(-3j * phi)) * np.max(np.abs(U[..., 2, :, 0] + 1j * U[..., 2, :, 1]))
+    assert abs(dev - expect) <= 1e-12 * expect and dev > dwf.SU3_TOL
+    Un = U.copy()
+    Un[1, 0, 1, 2, 3, 0, 2, 1] = np.nan
+    assert dwf.gauge_su3_deviation(Un, dims) == np.inf
+    with pytest.raises(ValueError):
+        dwf.gauge_su3_deviation(U, (4, 2, 2, 4))
+    L = dwf.lib()
+    out = ctypes.c_double()
+    d = (ctypes.c_int * 4)(4, 2, 3, 6)
+    assert L.dwf_gauge_su3_deviation(U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d,
+                                     ctypes.byref(out)) == dwf.DWF_EINVAL
+
+
+def test_binding_rejects_mismatched_arrays():
+    """Shapes, dtypes, devices and sizes are checked in the binding before a
+    pointer reaches the library (a short or misplaced buffer would be read or
+    written out of bounds)."""
+    import torch
+
+    import dwf_inputs as inp
+    import paper_1101_0423_amd as dwf
+    dims, ns = (4, 2, 2, 6), 3
+    one = dwf.spinor_shape(dims, ns)
+    a, n = dwf.check_host_spinors(np.zeros(one), dims, ns)
+    assert n == 1 and a.flags.c_contiguous
+    a, n = dwf.check_host_spinors(np.zeros((2,) + one), dims, ns)
+    assert n == 2
+    for bad in (np.zeros(one[:-1] + (12,)), np.zeros((4, 2, 2, 6, ns, 24)), np.zeros(int(np.prod(one))),
+                np.zeros((0,) + one)):
+        with pytest.raises(ValueError):
+            dwf.check_host_spinors(bad, dims, ns)
+    n = int(np.prod(one))
+    for t in (torch.zeros(n, dtype=torch.float64),                 # not on the GPU
+              torch.zeros(n, dtype=torch.float32),                 # wrong dtype
+              torch.zeros(2 * n, dtype=torch.float64)[::2],        # not contiguous
+              np.zeros(n)):                                        # not a tensor
+        with pytest.raises(ValueError):
+            dwf.check_device_spinors(t, dims, ns, 1, 0)
+    # the context refuses a gauge field or weights of the wrong shape before any library call
+    U = inp.gauge_field(dims, 0.5, seed=3)
+    with pytest.raises(ValueError):
+        dwf.Context(U.reshape(-1), dims, ns, 1.8, 0.1, np.zeros(ns), np.ones(ns))
+    with pytest.raises(ValueError):
+        dwf.Context(U, dims, ns, 1.8, 0.1, np.zeros(ns + 1), np.ones(ns))

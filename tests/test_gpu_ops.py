@@ -1,10 +1,15 @@
 """GPU operator parity: every dwf_apply operator against the FP64 oracle.
 
-Bars (norm-wise and element-wise relative to the oracle): FP64 1e-13, FP32
-1e-6, FP16 storage 2e-2 (binary16 keeps 11 significant bits per component
-relative to its site's largest component).  Shapes span several workgroups
-and a ragged last workgroup; the full 16^3x32x16 workload runs in the
-launch configuration the solver uses.
+Bars, norm-wise |got - exp| / |exp| and element-wise max|got - exp| / max|exp|:
+FP64 1e-13 and 4e-13; FP32 1e-6 and 4e-6, with 12-real links (what the FP32
+solver uses) and 18-real links alike; FP16 storage 3e-3 and 1.2e-2.  The FP16
+bar comes from the format: binary16 keeps 11 significant bits, so a component
+is stored to 2^-12 = 2.4e-4 of its site's largest component, and an operator
+such as C C^dag rounds its input, three intermediates and its output and reads
+binary16 links, each adding an error of that size (measured: see the printed
+values; the largest norm-wise error over these shapes is below 1.5e-3).
+Shapes span several workgroups and a ragged last workgroup; the full
+16^3x32x16 workload runs in the launch configuration the solver uses.
 """
 import numpy as np
 import pytest
@@ -15,7 +20,10 @@ from _util import Problem, max_rel, on_parity, rel
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-13, 1: 1e-6, 2: 2e-2}
+TOL = {0: 1e-13, 1: 1e-6, 2: 3e-3}              # norm-wise, by storage precision
+TOL_EL = {0: 4e-13, 1: 4e-6, 2: 1.2e-2}          # element-wise
+# storage precision | link storage (dwf_apply's prec argument)
+PRECS = {"fp64": 0, "fp32-12real": 1 | 0x200, "fp32-18real": 1 | 0x100, "fp16": 2}
 
 
 def problems():
@@ -87,17 +95,18 @@ def get_ctx(contexts, name):
 
 @pytest.mark.parametrize("name", list(PROBS))
 @pytest.mark.parametrize("op", OPS, ids=OP_NAMES)
-@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("prec", list(PRECS.values()), ids=list(PRECS))
 def test_operator_parity(contexts, name, op, prec):
     P = PROBS[name]
-    print(f"[ops] {name} {OP_NAMES[op]} prec={prec}", flush=True)
+    print(f"[ops] {name} {OP_NAMES[op]} prec={prec:#x}", flush=True)
     ctx = get_ctx(contexts, name)
     psi = P.b
     got = ctx.apply(op, psi, prec=prec)
     exp = oracle_op(P, op, psi)
-    tol = TOL[prec]
-    assert rel(got, exp) <= tol, (rel(got, exp), tol)
-    assert max_rel(got, exp) <= 4 * tol
+    e_n, e_el = rel(got, exp), max_rel(got, exp)
+    print(f"[ops]   error norm-wise {e_n:.3e}, element-wise {e_el:.3e}", flush=True)
+    assert e_n <= TOL[prec & 0xff], (e_n, TOL[prec & 0xff])
+    assert e_el <= TOL_EL[prec & 0xff], (e_el, TOL_EL[prec & 0xff])
     if prec == 0:
         # the parity a block operator does not touch is exactly zero
         import paper_1101_0423_amd as dwf
@@ -112,7 +121,7 @@ def test_multi_rhs_apply_equals_single(contexts):
     ctx = get_ctx(contexts, "ragged")
     bs = inp.gaussian_spinor(P.dims, P.ns, seed=99, nrhs=3)
     for op in (dwf.OP_C, dwf.OP_CDAG, dwf.OP_D):
-        for prec in (0, 1):
+        for prec in (0, PRECS["fp32-12real"], PRECS["fp32-18real"]):
             many = ctx.apply(op, bs, prec=prec)
             for k in range(3):
                 one = ctx.apply(op, bs[k], prec=prec)
@@ -154,7 +163,8 @@ def test_contexts_share_one_field():
 
 def test_full_size_operator_parity():
     """16^3x32, Ns = 16, the configuration of the primary solve: C, C^dag and D
-    in FP64 and FP32 against the oracle over the whole lattice."""
+    in FP64, FP32 (12-real links, the solver's, and 18-real) and FP16 storage
+    against the oracle over the whole lattice."""
     import paper_1101_0423_amd as dwf
     P = Problem.workload("odwf_16x16x16x32_ns16")
     ctx = P.context()
@@ -162,10 +172,12 @@ def test_full_size_operator_parity():
         for op in (dwf.OP_C, dwf.OP_CDAG, dwf.OP_D):
             print(f"[ops] full-size {OP_NAMES[op]}", flush=True)
             exp = oracle_op(P, op, P.b)
-            for prec in (0, 1):
+            for name, prec in PRECS.items():
                 got = ctx.apply(op, P.b, prec=prec)
-                assert rel(got, exp) <= TOL[prec], (op, prec, rel(got, exp))
-                assert max_rel(got, exp) <= 4 * TOL[prec]
+                e_n, e_el = rel(got, exp), max_rel(got, exp)
+                print(f"[ops]   {name}: norm-wise {e_n:.3e}, element-wise {e_el:.3e}", flush=True)
+                assert e_n <= TOL[prec & 0xff], (op, name, e_n)
+                assert e_el <= TOL_EL[prec & 0xff], (op, name, e_el)
     finally:
         ctx.close()
 
@@ -190,7 +202,7 @@ def _gammas():
     return g
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("prec", [0, PRECS["fp32-12real"], PRECS["fp32-18real"]], ids=["fp64", "fp32-12", "fp32-18"])
 @pytest.mark.parametrize("bct", [1.0, -1.0], ids=["periodic", "antiperiodic"])
 def test_unit_link_plane_waves_on_gpu(prec, bct):
     """With U = 1 the GPU's D_w (Eq. (2)) maps a plane wave e^{ipx} chi_s to
@@ -216,12 +228,12 @@ def test_unit_link_plane_waves_on_gpu(prec, bct):
             exp = phase * np.einsum("ij,sjc->sic", M, chi)
             got = _cplx(c.apply(dwf.OP_DW, _real(phase * chi), prec=prec), ns)
             err = np.linalg.norm(got - exp) / np.linalg.norm(exp)
-            assert err <= TOL[prec], (n, err)
+            assert err <= TOL[prec & 0xff], (n, err)
     finally:
         c.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("prec", [0, PRECS["fp32-12real"], PRECS["fp32-18real"]], ids=["fp64", "fp32-12", "fp32-18"])
 def test_gauge_covariance_on_gpu(prec):
     """D_w[U^g](g psi) = g D_w[U] psi and the same for the Schur operator C,
     U^g_mu(x) = g(x) U_mu(x) g(x + mu)^dag, on the GPU alone (two contexts,
@@ -247,7 +259,7 @@ def test_gauge_covariance_on_gpu(prec):
         for op in (dwf.OP_DW, dwf.OP_C):
             lhs = c2.apply(op, rot(psi), prec=prec)
             rhs = rot(c1.apply(op, psi, prec=prec))
-            assert rel(lhs, rhs) <= 2 * TOL[prec], (op, rel(lhs, rhs))
+            assert rel(lhs, rhs) <= 2 * TOL[prec & 0xff], (op, rel(lhs, rhs))
     finally:
         c1.close()
         c2.close()
@@ -261,7 +273,7 @@ TILED = Problem((24, 24, 2, 32), 16, 1.8, 0.02, *(2 * [_rng_t.uniform(0.5, 1.5, 
 _TILED_EXP = {}
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("prec", [0, PRECS["fp32-12real"], PRECS["fp32-18real"]], ids=["fp64", "fp32-12", "fp32-18"])
 def test_tiled_block_order_parity(prec):
     """Operators on a lattice whose z-planes are walked in tiles of workgroups
     equal the oracle's: every block is visited exactly once in that order."""
@@ -275,7 +287,39 @@ def test_tiled_block_order_parity(prec):
                 _TILED_EXP[op] = oracle_op(TILED, op, TILED.b)
             got = c.apply(op, TILED.b, prec=prec)
             exp = _TILED_EXP[op]
-            assert rel(got, exp) <= TOL[prec], (OP_NAMES[op], rel(got, exp))
-            assert max_rel(got, exp) <= 4 * TOL[prec], OP_NAMES[op]
+            assert rel(got, exp) <= TOL[prec & 0xff], (OP_NAMES[op], rel(got, exp))
+            assert max_rel(got, exp) <= TOL_EL[prec & 0xff], OP_NAMES[op]
+    finally:
+        c.close()
+
+
+def test_non_su3_field_uses_18_real_links():
+    """A U(3) field (every link times e^{i phi}): 12-real storage would rebuild a
+    different third row, so the library refuses it (12-real links, FP16
+    storage), its FP32 default uses 18-real links and still meets the FP32
+    bar, and a solve with the default parameters meets the solve bar."""
+    import paper_1101_0423_amd as dwf
+    P = PROBS["ragged"]
+    z = (P.U[..., 0] + 1j * P.U[..., 1]) * np.exp(0.3j)
+    U3 = np.stack([z.real, z.imag], axis=-1)
+    assert dwf.gauge_su3_deviation(U3, P.dims) > dwf.SU3_TOL
+    c = dwf.Context(U3, *P.args, antiperiodic_t=True)
+    try:
+        for prec in (PRECS["fp32-12real"], PRECS["fp16"]):
+            with pytest.raises(dwf.DwfError) as ei:
+                c.apply(dwf.OP_C, P.b, prec=prec)
+            assert ei.value.code == dwf.DWF_EINVAL
+        for kw in (dict(inner_prec=1, link_compress=1), dict(inner_prec=2)):
+            with pytest.raises(dwf.DwfError) as ei:
+                c.solve(P.b, **kw)
+            assert ei.value.code == dwf.DWF_EINVAL
+        a = (U3, P.dims, P.ns, P.m0, P.mq, P.sigma, P.omega)
+        exp = oracle.schur_c(*a, on_parity(P.b, P.dims, 1), bct=P.bct)
+        auto = c.apply(dwf.OP_C, P.b, prec=1)
+        assert np.array_equal(auto, c.apply(dwf.OP_C, P.b, prec=PRECS["fp32-18real"]))
+        assert rel(auto, exp) <= TOL[1], rel(auto, exp)
+        x, st, rc = c.solve(P.b)
+        assert rc == dwf.DWF_OK, st
+        assert oracle.true_residual(*a, P.b, x, bct=P.bct) <= 1e-10
     finally:
         c.close()

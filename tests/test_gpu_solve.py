@@ -173,12 +173,13 @@ def test_full_size_solve(name, prec, lc):
         assert rc == dwf.DWF_OK, st
         check(P, x)
         g = _golden(name)
-        if g is not None:
-            got = x.ravel()[np.asarray(g["indices"])]
-            exp = np.asarray(g["values"])
-            # forward error measured on the sampled entries, relative to |x|
-            err = np.linalg.norm(got - exp) / (np.linalg.norm(exp))
-            assert err <= TOL_FWD, err
+        assert g is not None, "stored oracle samples missing"
+        got = x.ravel()[np.asarray(g["indices"])]
+        exp = np.asarray(g["values"])
+        # forward error measured on the sampled entries, relative to |x|
+        err = np.linalg.norm(got - exp) / (np.linalg.norm(exp))
+        print(f"[solve]   forward error on the oracle's samples {err:.3e}", flush=True)
+        assert err <= TOL_FWD, err
     finally:
         c.close()
 
@@ -187,9 +188,9 @@ def test_full_size_solve(name, prec, lc):
 def test_full_size_batched_point_sources():
     """The batched workload (24^3x48, Ns = 16 Shamir, mq = 0.005, 12 point
     sources) in the launch configuration of the benchmark: one 12-right-hand-
-    side solve.  Every source converges (the solver's FP64 check of
-    ||b - D x|| / ||b|| <= 1e-10); source 0 meets that bar with the oracle's
-    operator, and its forward error against the oracle's stored samples is
+    side solve.  Every source meets ||b - D x|| / ||b|| <= 1e-10 both in the
+    solver's own FP64 check and with the oracle's operator on the returned x;
+    source 0's forward error against the oracle's stored samples is
     <= 1e-8.  The point-source solution is concentrated near the source, so
     the uniform samples carry little of its norm: the error is measured as the
     unbiased estimate of the global relative error,
@@ -218,14 +219,18 @@ def test_full_size_batched_point_sources():
         assert rc == dwf.DWF_OK, st
         for s in st:
             assert s["status"] == dwf.DWF_OK and s["true_residual"] <= TOL_RES, s
-        x0 = X[0].cpu().numpy()
+        # every source with the oracle's operator (one 2 GB spinor at a time)
+        for k in range(12):
+            xk = X[k].cpu().numpy()
+            if k == 0:
+                x0 = xk
+            bk = inp.point_source(dims, ns, k, seed=w["seed_rhs"])
+            res = oracle.true_residual(U, *oargs, bk, xk)
+            print(f"oracle true residual of source {k}: {res:.3e}", flush=True)
+            assert res <= TOL_RES, (k, res)
         del B, X
     finally:
         c.close()
-    b0 = inp.point_source(dims, ns, 0, seed=w["seed_rhs"])
-    res = oracle.true_residual(U, *oargs, b0, x0)
-    print(f"oracle true residual of source 0: {res:.3e}", flush=True)
-    assert res <= TOL_RES, res
     idx = np.asarray(g["indices"])
     e = x0.ravel()[idx] - np.asarray(g["values"])
     err = np.sqrt(x0.size / idx.size) * np.linalg.norm(e) / g["norm_x"]
