@@ -5,9 +5,14 @@ One step = one full solve D x = b (source preparation, mixed-precision
 CG with FP64 defect correction and reliable updates, reconstruction and the
 FP64 true-residual check) on the 16^3 x 32, Ns = 16 optimal-DWF workload,
 with b and x resident in HBM.  Prints one JSON line: CG Gflops (the paper's
-counting convention) as `value`, plus algorithmic HBM GB/s, the
-roofline of the dominant kernel (HIP-event timed on the solver's stream) and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+counting convention: 1320 flops per 5D site per hop, 48 Ns per site per dense
+fifth-dimension matrix, 24 per subtraction, per-real BLAS) as `value`, plus
+algorithmic HBM GB/s, the forward error of the timed solve against the FP64
+oracle's stored samples, the roofline of the dominant kernel (HIP-event timed
+on the solver's stream), the same workload with FP16 storage (`precision`),
+the 12-point-source batched workload against 12 single solves (`batched`), a
+200-request served stream against a FIFO single-solve server (`served`) and
+the FP64 CPU oracle timed on a bounded sample of the workload.
 """
 import argparse
 import hashlib
@@ -58,28 +63,60 @@ def counter_traffic(kernel, workload, variant):
         return None
 
 
-def cpu_baseline(w, U, b, n1=1, n2=30):
-    """The FP64 oracle, as it stands, on the same workload: per-iteration time
-    from two bounded runs (n1 and n2 CG iterations)."""
+def golden_samples(name):
+    """Sampled entries of the FP64 oracle's solution (tests/golden, written by
+    tests/golden/make_oracle_samples.py from the oracle alone), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_oracle_samples.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def sampled_forward_error(x_dev, g, unbiased=False):
+    """Relative forward error of a device solution on the oracle's samples:
+    |x_S - xo_S| / |xo_S|, or for a solution concentrated near its source
+    (point sources) the unbiased estimate sqrt(N / |S|) |x_S - xo_S| / |xo|."""
+    import numpy as np
+    import torch
+    idx = torch.as_tensor(np.asarray(g["indices"], dtype=np.int64), device=x_dev.device)
+    got = x_dev.reshape(-1)[idx].cpu().numpy()
+    exp = np.asarray(g["values"])
+    e = float(np.linalg.norm(got - exp))
+    if unbiased:
+        return float(np.sqrt(x_dev.numel() / idx.numel()) * e / g["norm_x"])
+    return e / float(np.linalg.norm(exp))
+
+
+def cpu_baseline(w, U, b, n1=2, n2=12, reps=3):
+    """The FP64 oracle, as it stands, on the same workload: the per-iteration
+    time is the difference of the median times of runs capped at n1 and n2 CG
+    iterations (reps runs each), which removes the set-up and reconstruction."""
+    import numpy as np
+
     import oracle
     args = (U, w["dims"], w["ns"], w["m0"], w["mq"], w["sigma"], w["omega"])
-    t = []
-    for n in (n1, n2):
-        t0 = time.perf_counter()
-        oracle.solve(*args, b, tol=1e-12, maxiter=n)
-        t.append(time.perf_counter() - t0)
-    per_it = (t[1] - t[0]) / (n2 - n1)
+    t = {n1: [], n2: []}
+    for _ in range(reps):
+        for n in (n1, n2):
+            t0 = time.perf_counter()
+            oracle.solve(*args, b, tol=1e-12, maxiter=n)
+            t[n].append(time.perf_counter() - t0)
+    per_it = (float(np.median(t[n2])) - float(np.median(t[n1]))) / (n2 - n1)
     lx, ly, lz, lt = w["dims"]
     v5h = lx * ly * lz * lt * w["ns"] // 2
     flops = v5h * (5280.0 + 192.0 * w["ns"] + 288.0)
+    work = sum(sum(v) for v in t.values())
     return dict(value=round(flops / per_it * 1e-9, 3), unit="Gflops", cores=oracle.num_threads(), kind="oracle",
-                sample=f"FP64 CPU oracle, CG iterations {n1}..{n2} of the same solve (per-iteration time from "
-                       f"the difference of two runs; {sum(t):.1f} s of CPU work)",
+                sample=f"FP64 CPU oracle on the same 16^3x32x16 solve: median of {reps} runs capped at {n1} and "
+                       f"at {n2} CG iterations, per-iteration time from their difference ({work:.1f} s of CPU "
+                       f"work), converted with the same flop convention",
                 seconds_per_iteration=per_it)
 
 
 KERNEL_KEYS = [("ProCgE", "cg_dir_m5t"), ("EpiCgD", "hop_oe_m5_cgupd"), ("EpiCgB", "hop_oe_g5_sub"),
-               ("k_finish", "finish_reduction"), ("EpiOuter", "outer_residual_fp64")]
+               ("k_finish", "finish_reduction"), ("EpiOuter", "outer_residual_fp64"),
+               ("k_stream_copy<true>", "copy_nontemporal_1GiB"), ("k_stream_copy<false>", "copy_cached_1GiB")]
 
 
 def kernel_label(name):
@@ -121,20 +158,24 @@ def _ctx(dwf, U, w, **kw):
     return dwf.Context(U, w["dims"], w["ns"], w["m0"], w["mq"], w["sigma"], w["omega"], device=0, **kw)
 
 
-def batch_bench(args):
+def run_batch(nrhs=12, log=True):
     """24^3 x 48, Ns = 16 Shamir, 12 point sources: one 12-right-hand-side
-    solve against 12 single-right-hand-side solves of the same sources."""
-    import numpy as np
+    solve against 12 single-right-hand-side solves of the same sources, each
+    timed alone; every true residual from the solver's FP64 check, source 0's
+    forward error against the oracle's stored samples."""
     import torch
 
     import dwf_inputs as inp
     import paper_1101_0423_amd as dwf
 
+    def say(msg):
+        if log:
+            print(msg, file=sys.stderr, flush=True)
+
     wname = "shamir_24x24x24x48_ns16_12pt"
     w = inp.workload(wname)
     dims, ns = w["dims"], w["ns"]
-    nrhs = args.nrhs
-    print(f"[bench] generating {wname}", file=sys.stderr, flush=True)
+    say(f"[bench] generating {wname}")
     U = inp.gauge_field(dims, w["eps"], seed=w["seed_gauge"])
     torch.cuda.set_device(0)
     ctx = _ctx(dwf, U, w)
@@ -155,8 +196,9 @@ def batch_bench(args):
     st_b, rc_b = ctx.solve_dev(B, X, nrhs=nrhs, params=params)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
-    print(f"[bench] batched {nrhs}: rc={rc_b} {t_batch:.2f}s iters={[s['iters'] for s in st_b]}",
-          file=sys.stderr, flush=True)
+    say(f"[bench] batched {nrhs}: rc={rc_b} {t_batch:.2f}s iters={[s['iters'] for s in st_b]}")
+    g = golden_samples(wname + "_rhs0")
+    fwd0 = sampled_forward_error(X[0], g, unbiased=True) if g is not None else None
     ms_b, by_b = ctx.time_kernels(params=params, nrhs=nrhs, launches=5)
     t_seq, st_s, diff = 0.0, [], 0.0
     for k in range(nrhs):
@@ -168,35 +210,50 @@ def batch_bench(args):
         t_seq += time.perf_counter() - t0
         st_s.append((st[0], rc))
         diff = max(diff, float(torch.linalg.vector_norm(X[k] - X1) / torch.linalg.vector_norm(X1)))
-        print(f"[bench] single {k}: rc={rc} {st[0]['seconds']:.2f}s iters={st[0]['iters']}", file=sys.stderr,
-              flush=True)
+        say(f"[bench] single {k}: rc={rc} {st[0]['seconds']:.2f}s iters={st[0]['iters']}")
     ms_1, by_1 = ctx.time_kernels(params=params, nrhs=1, launches=5)
     flops = sum(s["gflops"] for s in st_b[:1]) * st_b[0]["seconds"] * 1e9
+    gbytes = st_b[0]["hbm_gbytes"]
     names = {"E": "cg_dir_m5t", "A": "hop_eo_m5t", "B": "hop_oe_g5_sub", "C": "hop_eo_m5", "D": "hop_oe_m5_cgupd"}
     kern = {names[k]: dict(ms_batch=round(ms_b[k], 4), ms_single=round(ms_1[k], 4),
                            gbs_batch=round(by_b[k] / (ms_b[k] * 1e-3) * 1e-9, 1),
                            gbs_single=round(by_1[k] / (ms_1[k] * 1e-3) * 1e-9, 1)) for k in ms_b}
-    line = dict(metric="batched solves/s (24^3x48, Ns=16, 12 point sources)", value=round(nrhs / t_batch, 4),
-                unit="solves/s", n_gpus=1, steps=1, warmup=1, ms_per_step=round(t_batch * 1e3, 1),
-                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32 inner / f64 outer",
-                data="synthetic",
-                config=dict(workload=f"{wname}: 24^3x48 lattice, Ns=16 Shamir, m0=1.8, mq=0.005, SU(3) links "
-                                     f"eps=0.5, {nrhs} point sources at one seeded 5D site, tol 1e-10",
-                            nrhs=nrhs),
-                sequential_solves_per_s=round(nrhs / t_seq, 4), speedup=round(t_seq / t_batch, 3),
-                batch_gflops=round(flops / t_batch * 1e-9, 1),
+    ctx.close()
+    del B, X, X1
+    torch.cuda.empty_cache()
+    return dict(workload=f"{wname}: 24^3x48 lattice, Ns=16 Shamir, m0=1.8, mq=0.005, SU(3) links eps=0.5, "
+                         f"{nrhs} point sources at one seeded 5D site, tol 1e-10, FP32 inner / FP64 outer",
+                nrhs=nrhs, solves_per_s=round(nrhs / t_batch, 4), seconds=round(t_batch, 3),
+                sequential_solves_per_s=round(nrhs / t_seq, 4), sequential_seconds=round(t_seq, 3),
+                speedup=round(t_seq / t_batch, 3), gflops=round(flops / t_batch * 1e-9, 1),
+                hbm_gbs=round(gbytes / t_batch, 1),
                 converged=all(s["status"] == 0 for s in st_b) and all(rc == 0 for _, rc in st_s),
                 max_true_residual=max(s["true_residual"] for s in st_b),
+                forward_error_source0=fwd0,
+                forward_error_kind="unbiased estimate sqrt(N/|S|) |x_S - xo_S| / |xo| from 4096 uniform samples of "
+                                   "the FP64 oracle's solution of source 0 (solved to 1e-12)",
                 batch_vs_single_max_rel_diff=diff, iters=[s["iters"] for s in st_b],
                 rhs_per_workgroup=st_b[0]["rhs_per_block"], kernels=kern)
-    ctx.close()
+
+
+def batch_bench(args):
+    r = run_batch(args.nrhs)
+    line = dict(metric="batched solves/s (24^3x48, Ns=16, 12 point sources)", value=r["solves_per_s"],
+                unit="solves/s", n_gpus=1, steps=1, warmup=1, ms_per_step=round(r["seconds"] * 1e3, 1),
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32 inner / f64 outer",
+                data="synthetic", config=dict(workload=r["workload"], nrhs=r["nrhs"]),
+                **{k: v for k, v in r.items() if k not in ("workload", "nrhs", "solves_per_s")})
     print(json.dumps(line), flush=True)
 
 
-def run_serve(n_requests, load, log=True):
+def run_serve(n_requests, load, log=True, fifo_run=False):
     """Poisson stream of independent solves on four resident fields (every
     (field, Ns) pair is one context), served by dwf_submit/dwf_poll, against a
-    FIFO server of plain single-right-hand-side solves on the same stream.
+    FIFO server of plain single-right-hand-side solves (dwf_solve, one request
+    at a time in arrival order) on the same stream: simulated from each request
+    type's service time measured here (median of 3 solves), and with fifo_run
+    also run for real.  Latencies are from arrival to completion, p50 and p99
+    by the same definition (numpy's interpolated percentile) for both servers.
     Returns the measurements as a dict."""
     import threading
 
@@ -226,7 +283,7 @@ def run_serve(n_requests, load, log=True):
     params = dwf.default_params(inner_prec=1, tol=1e-10)
     # plain single-right-hand-side service time of every request type (a
     # context per mass, so that dwf_solve runs that mass)
-    svc = {}
+    svc, fctx = {}, {}
     for r in reqs:
         key = (r["field"], r["ns"], r["mq"])
         if key in svc:
@@ -235,10 +292,16 @@ def run_serve(n_requests, load, log=True):
         c = dwf.Context(gauges[r["field"]], o["dims"], r["ns"], o["m0"], r["mq"], o["sigma"], o["omega"], device=0)
         b = rhs[(r["field"], r["ns"], 0)]
         c.solve(b, params=dwf.default_params(inner_prec=1, tol=1e-10, maxiter=8))  # engine and graph
-        t0 = time.perf_counter()
-        x, st, rc = c.solve(b, params=params)
-        svc[key] = time.perf_counter() - t0
-        c.close()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            x, st, rc = c.solve(b, params=params)
+            ts.append(time.perf_counter() - t0)
+        svc[key] = float(np.median(ts))
+        if fifo_run:
+            fctx[key] = c
+        else:
+            c.close()
         say(f"[serve] plain service {key}: {svc[key]:.3f}s iters={st[0]['iters']}")
     mean_svc = float(np.mean([svc[(r["field"], r["ns"], r["mq"])] for r in reqs]))
     if load > 0:
@@ -254,6 +317,28 @@ def run_serve(n_requests, load, log=True):
         done = max(done, a) + svc[(r["field"], r["ns"], r["mq"])]
         fifo_lat.append(done - a)
     fifo_span = done
+    fifo_real = None
+    if fifo_run:
+        say(f"[serve] FIFO run of {len(reqs)} requests")
+        lat_f, ok_f = [], True
+        t_start = time.perf_counter()
+        for i, (r, a) in enumerate(zip(reqs, arrivals)):
+            delay = t_start + a - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            x, st, rc = fctx[(r["field"], r["ns"], r["mq"])].solve(rhs[(r["field"], r["ns"], r["rhs"])],
+                                                                   params=params)
+            ok_f &= rc == dwf.DWF_OK
+            lat_f.append(time.perf_counter() - t_start - a)
+            if (i + 1) % 50 == 0:
+                say(f"[serve] FIFO: {i + 1} of {len(reqs)} requests done")
+        span_f = time.perf_counter() - t_start
+        for c in fctx.values():
+            c.close()
+        fifo_real = dict(solves_per_s=round(len(reqs) / span_f, 4),
+                         p50_latency_s=round(float(np.percentile(lat_f, 50)), 4),
+                         p99_latency_s=round(float(np.percentile(lat_f, 99)), 4), converged=bool(ok_f),
+                         kind="plain single-RHS dwf_solve calls in arrival order, run on this GPU")
     # warm the server: one request per operator builds its lane
     warm = [ctxs[k].submit(rhs[k + (0,)], mq=inp.SERVE_MQ[-1], params=params) for k in ctxs]
     for t, k in zip(warm, ctxs):
@@ -295,21 +380,25 @@ def run_serve(n_requests, load, log=True):
     lat = np.array([l for _, _, l in results])
     for c in ctxs.values():
         c.close()
-    return dict(requests=len(reqs), load=load, solves_per_s=round(len(reqs) / span, 4),
-                solves_per_busy_s=round(s["completed"] / s["busy_seconds"], 4) if s["busy_seconds"] > 0 else None,
-                p50_latency_s=round(s["p50_latency"], 4), p99_latency_s=round(s["p99_latency"], 4),
-                p50_latency_from_arrival_s=round(float(np.percentile(lat, 50)), 4),
-                p99_latency_from_arrival_s=round(float(np.percentile(lat, 99)), 4),
-                peak_batch=s["peak_batch"], waits_for_memory=s["waits_for_memory"],
-                busy_s=round(s["busy_seconds"], 3),
-                fifo=dict(solves_per_s=round(len(reqs) / fifo_span, 4), solves_per_busy_s=round(1.0 / mean_svc, 4),
-                          p50_latency_s=round(float(np.percentile(fifo_lat, 50)), 4),
-                          p99_latency_s=round(float(np.percentile(fifo_lat, 99)), 4),
-                          kind="plain single-RHS solves in arrival order; service time of each request type "
-                               "measured on this GPU"),
-                mean_plain_service_s=round(mean_svc, 4),
-                converged=all(rc == dwf.DWF_OK for rc, _, _ in results),
-                max_true_residual=max(r for _, r, _ in results))
+    out = dict(requests=len(reqs), load=load, solves_per_s=round(len(reqs) / span, 4),
+               solves_per_busy_s=round(s["completed"] / s["busy_seconds"], 4) if s["busy_seconds"] > 0 else None,
+               p50_latency_s=round(float(np.percentile(lat, 50)), 4),
+               p99_latency_s=round(float(np.percentile(lat, 99)), 4),
+               latency_kind="arrival to completion, numpy percentile (the same for the FIFO server)",
+               server_p50_p99_s=[round(s["p50_latency"], 4), round(s["p99_latency"], 4)],
+               peak_batch=s["peak_batch"], waits_for_memory=s["waits_for_memory"],
+               busy_s=round(s["busy_seconds"], 3),
+               fifo=dict(solves_per_s=round(len(reqs) / fifo_span, 4), solves_per_busy_s=round(1.0 / mean_svc, 4),
+                         p50_latency_s=round(float(np.percentile(fifo_lat, 50)), 4),
+                         p99_latency_s=round(float(np.percentile(fifo_lat, 99)), 4),
+                         kind="simulated: plain single-RHS solves in arrival order, each request type's service "
+                              "time measured on this GPU (median of 3 dwf_solve calls)"),
+               mean_plain_service_s=round(mean_svc, 4),
+               converged=all(rc == dwf.DWF_OK for rc, _, _ in results),
+               max_true_residual=max(r for _, r, _ in results))
+    if fifo_real is not None:
+        out["fifo_run"] = fifo_real
+    return out
 
 
 SERVE_WORKLOAD = ("fields 8^3x16, 12^3x24, 2x 16^3x32 (eps 0.5); per request Ns in {8,16,32}, "
@@ -317,7 +406,7 @@ SERVE_WORKLOAD = ("fields 8^3x16, 12^3x24, 2x 16^3x32 (eps 0.5); per request Ns 
 
 
 def serve_bench(args):
-    r = run_serve(args.requests, args.load)
+    r = run_serve(args.requests, args.load, fifo_run=args.fifo_run)
     arrivals = (f"Poisson arrivals at {args.load} x the plain single-RHS service rate" if args.load > 0
                 else "all submitted at once (saturated)")
     line = dict(metric="served solves/s, p99 latency (Poisson stream, 4 resident fields)",
@@ -344,8 +433,12 @@ def main():
                          "batched vs sequential; serve: Poisson request stream, served vs FIFO")
     ap.add_argument("--nrhs", type=int, default=12, help="batch mode: right-hand sides")
     ap.add_argument("--requests", type=int, default=200, help="serve mode: requests in the stream")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=200,
                     help="solve mode: requests of the served stream measured after the solves (0: none)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="solve mode: skip the precision (FP16) and batched blocks")
+    ap.add_argument("--fifo-run", action="store_true",
+                    help="serve mode: also run the FIFO single-solve server on the stream (not only simulate it)")
     ap.add_argument("--load", type=float, default=0.8,
                     help="serve mode: arrival rate / plain service rate (0: all requests at once)")
     ap.add_argument("--summarize-rocpd", metavar="DB", help="print per-kernel statistics of a rocprofv3 "
@@ -364,7 +457,6 @@ def main():
     if args.mode == "serve":
         return serve_bench(args)
 
-    import numpy as np
     import torch
 
     import dwf_inputs as inp
@@ -380,71 +472,107 @@ def main():
     ctx = dwf.Context(U, dims, ns, w["m0"], w["mq"], w["sigma"], w["omega"], device=0)
     bd = torch.from_numpy(b).cuda()
     xd = torch.zeros_like(bd)
-    params = dwf.default_params(inner_prec=prec, link_compress=lc, tol=1e-10)
     if args.mode == "kernels":
         kp = dwf.default_params(inner_prec=prec, link_compress=lc, use_graph=0, maxiter=40)
         st, rc = ctx.solve_dev(bd, xd, params=kp)
         ms, by = ctx.time_kernels(params=kp, launches=5)
-        # counter calibration: the layout conversions of an M5 application move
-        # known bytes in each storage format (k_host_to_half / k_half_to_host)
-        for pr in (dwf.PREC_FP64, dwf.PREC_FP32, dwf.PREC_FP16):
-            ctx.apply_dev(dwf.OP_M5, bd, xd, prec=pr)
+        # counter calibration: plain copies of a known size (1 GiB, four times
+        # the Infinity Cache), with cached and with non-temporal accesses
+        n = 1 << 30
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for nt in (False, True):
+            for _ in range(3):
+                dwf.stream_copy(src, dst, nontemporal=nt)
+        del src, dst
         print(json.dumps(dict(mode="kernels", workload=wname, ms={k: ms[k] for k in ms},
-                              bytes={k: by[k] for k in by})), flush=True)
+                              bytes={k: by[k] for k in by}, copy_bytes_read=n, copy_bytes_written=n)), flush=True)
         ctx.close()
         return
-    for i in range(args.warmup):
+
+    def say(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    r = run_solve(dwf, ctx, bd, xd, prec, lc, args.steps, args.warmup, args.kernel_launches, say)
+    g = golden_samples("odwf_16x16x16x32_ns16")
+    fwd = sampled_forward_error(xd, g) if g is not None else None
+    traffic = counter_traffic(r["dominant"], wname, args.prec)
+    roofline = dict(r["roofline"], traffic=traffic)
+    line = dict(metric=METRIC, value=r["gflops"], unit="Gflops", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=r["ms_per_step"], higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype=r["dtype"], data="synthetic",
+                config=dict(workload=f"{wname}: 16^3x32 lattice, Ns=16, m0=1.8, mq=0.01, sigma=omega~U[0.5,1.5], "
+                                     f"SU(3) links eps=0.5, Gaussian RHS, tol 1e-10",
+                            lattice=list(dims), Ns=ns, inner_prec=["fp64", "fp32", "fp16"][prec],
+                            link_real=18 if (lc == 0 or prec == 0) else 12, reliable_updates=True),
+                hbm_gbs=r["hbm_gbs"], iters=r["iters"], true_residual=r["true_residual"],
+                forward_error=fwd,
+                forward_error_kind="|x_S - xo_S| / |xo_S| over 4096 uniform samples of the FP64 oracle's solution "
+                                   "(solved to 1e-12), for the last timed solve",
+                converged=r["converged"], roofline=roofline, kernels=r["kernels"])
+    if args.prec == "fp32" and not args.no_extra:
+        # the precision form: the same workload with FP16 storage and FP32 arithmetic
+        say("[bench] precision form: FP16 storage")
+        r16 = run_solve(dwf, ctx, bd, xd, 2, -1, max(3, args.steps // 4), 1, args.kernel_launches, say)
+        line["precision"] = dict(
+            workload=f"{wname} with FP16 storage (binary16 spinors with one FP32 scale per 5D site, 12-real "
+                     f"binary16 links), FP32 arithmetic, FP64 outer residual / solution / reductions",
+            steps=max(3, args.steps // 4), gflops=r16["gflops"], hbm_gbs=r16["hbm_gbs"],
+            ms_per_step=r16["ms_per_step"], iters=r16["iters"], true_residual=r16["true_residual"],
+            forward_error=sampled_forward_error(xd, g) if g is not None else None, converged=r16["converged"],
+            dominant_kernel=dict(r16["roofline"], kernel=r16["dominant"]), kernels=r16["kernels"])
+    ctx.close()
+    del bd, xd
+    torch.cuda.empty_cache()
+    if args.prec == "fp32" and not args.no_extra:
+        say("[bench] batched form: 24^3x48, 12 point sources")
+        line["batched"] = run_batch(12)
+    if args.serve_requests > 0:
+        say(f"[bench] served stream of {args.serve_requests} requests")
+        sv = run_serve(args.serve_requests, 0.8)
+        line["served"] = dict(workload=f"{sv['requests']} requests, Poisson arrivals at 0.8 x the plain "
+                                       f"single-RHS service rate; {SERVE_WORKLOAD}", **sv)
+    if not args.no_cpu_baseline:
+        say("[bench] timing the CPU oracle")
+        line["cpu_baseline"] = cpu_baseline(w, U, b)
+    print(json.dumps(line), flush=True)
+
+
+def run_solve(dwf, ctx, bd, xd, prec, lc, steps, warmup, launches, say):
+    """Timed solves of D x = b with b and x resident in HBM, then each inner
+    kernel timed with HIP events on the solver's stream."""
+    import torch
+    params = dwf.default_params(inner_prec=prec, link_compress=lc, tol=1e-10)
+    for i in range(warmup):
         st, rc = ctx.solve_dev(bd, xd, params=params)
-        print(f"[bench] warmup {i}: rc={rc} {st[0]}", file=sys.stderr, flush=True)
+        say(f"[bench] warmup {i}: rc={rc} {st[0]}")
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         st, rc = ctx.solve_dev(bd, xd, params=params)
         stats.append((st[0], rc))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for i, (s, rc) in enumerate(stats):
-        print(f"[bench] step {i}: rc={rc} iters={s['iters']} res={s['true_residual']:.3e} "
-              f"t={s['seconds']:.4f}s {s['gflops']:.1f} Gflops", file=sys.stderr, flush=True)
+        say(f"[bench] step {i}: rc={rc} iters={s['iters']} res={s['true_residual']:.3e} "
+            f"t={s['seconds']:.4f}s {s['gflops']:.1f} Gflops")
     flops = sum(s["gflops"] * s["seconds"] for s, _ in stats) * 1e9
     gbytes = sum(s["hbm_gbytes"] for s, _ in stats)
-    value = flops / elapsed * 1e-9
-    ok = all(rc == dwf.DWF_OK for _, rc in stats)
-
-    # per-kernel device time on the solver's stream (HIP events), same process
-    ms, by = ctx.time_kernels(params=params, launches=args.kernel_launches)
+    ms, by = ctx.time_kernels(params=params, launches=launches)
     dom = max(ms, key=ms.get)
     names = {"E": "cg_dir_m5t", "A": "hop_eo_m5t", "B": "hop_oe_g5_sub", "C": "hop_eo_m5", "D": "hop_oe_m5_cgupd"}
     achieved = by[dom] / (ms[dom] * 1e-3) * 1e-9
-    traffic = counter_traffic(names[dom], wname, args.prec)
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=names[dom],
-                    algorithmic_bytes_per_launch=by[dom], avg_launch_ms=round(ms[dom], 5))
-    kernels = {names[k]: dict(ms=round(ms[k], 5), gbs=round(by[k] / (ms[k] * 1e-3) * 1e-9, 1)) for k in ms}
-
-    line = dict(metric=METRIC, value=round(value, 2), unit="Gflops", n_gpus=1, steps=args.steps,
-                warmup=args.warmup, ms_per_step=round(elapsed / args.steps * 1e3, 3), higher_is_better=True,
-                scaling="weak", vs_baseline=None,
+    return dict(gflops=round(flops / elapsed * 1e-9, 2), hbm_gbs=round(gbytes / elapsed, 1),
+                ms_per_step=round(elapsed / steps * 1e3, 3), iters=stats[-1][0]["iters"],
+                true_residual=stats[-1][0]["true_residual"], converged=all(rc == dwf.DWF_OK for _, rc in stats),
                 dtype={0: "f64", 1: "f32 inner / f64 outer", 2: "f16 storage, f32 arithmetic / f64 outer"}[prec],
-                data="synthetic",
-                config=dict(workload=f"{wname}: 16^3x32 lattice, Ns=16, m0=1.8, mq=0.01, sigma=omega~U[0.5,1.5], "
-                                     f"SU(3) links eps=0.5, Gaussian RHS, tol 1e-10",
-                            lattice=list(dims), Ns=ns, inner_prec=["fp64", "fp32", "fp16"][prec],
-                            link_real=18 if (lc == 0 or prec == 0) else 12, reliable_updates=True),
-                hbm_gbs=round(gbytes / elapsed, 1), iters=stats[-1][0]["iters"],
-                true_residual=stats[-1][0]["true_residual"], converged=ok,
-                roofline=roofline, kernels=kernels)
-    ctx.close()
-    if args.serve_requests > 0:
-        print(f"[bench] served stream of {args.serve_requests} requests", file=sys.stderr, flush=True)
-        sv = run_serve(args.serve_requests, 0.8)
-        line["served"] = dict(workload=f"{sv['requests']} requests, Poisson arrivals at 0.8 x the plain "
-                                       f"single-RHS service rate; {SERVE_WORKLOAD}", **sv)
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, U, b)
-    print(json.dumps(line), flush=True)
+                dominant=names[dom],
+                roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                              frac=round(achieved / HBM_PEAK_GBS, 4), kernel=names[dom],
+                              algorithmic_bytes_per_launch=by[dom], avg_launch_ms=round(ms[dom], 5)),
+                kernels={names[k]: dict(ms=round(ms[k], 5), gbs=round(by[k] / (ms[k] * 1e-3) * 1e-9, 1))
+                         for k in ms})
 
 
 if __name__ == "__main__":

@@ -2,12 +2,13 @@
 
 Bars, norm-wise |got - exp| / |exp| and element-wise max|got - exp| / max|exp|:
 FP64 1e-13 and 4e-13; FP32 1e-6 and 4e-6, with 12-real links (what the FP32
-solver uses) and 18-real links alike; FP16 storage 3e-3 and 1.2e-2.  The FP16
+solver uses) and 18-real links alike; FP16 storage 1e-3 and 1.5e-3.  The FP16
 bar comes from the format: binary16 keeps 11 significant bits, so a component
 is stored to 2^-12 = 2.4e-4 of its site's largest component, and an operator
-such as C C^dag rounds its input, three intermediates and its output and reads
-binary16 links, each adding an error of that size (measured: see the printed
-values; the largest norm-wise error over these shapes is below 1.5e-3).
+such as C C^dag rounds its input, its intermediates and its output and reads
+binary16 links, each adding an error of that size.  Measured over these shapes
+and the full 16^3x32x16 lattice: at most 3.8e-4 norm-wise and 5.4e-4
+element-wise (printed by each case), so the bars leave a factor 2.6-2.8.
 Shapes span several workgroups and a ragged last workgroup; the full
 16^3x32x16 workload runs in the launch configuration the solver uses.
 """
@@ -20,8 +21,8 @@ from _util import Problem, max_rel, on_parity, rel
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-13, 1: 1e-6, 2: 3e-3}              # norm-wise, by storage precision
-TOL_EL = {0: 4e-13, 1: 4e-6, 2: 1.2e-2}          # element-wise
+TOL = {0: 1e-13, 1: 1e-6, 2: 1e-3}              # norm-wise, by storage precision
+TOL_EL = {0: 4e-13, 1: 4e-6, 2: 1.5e-3}          # element-wise
 # storage precision | link storage (dwf_apply's prec argument)
 PRECS = {"fp64": 0, "fp32-12real": 1 | 0x200, "fp32-18real": 1 | 0x100, "fp16": 2}
 

@@ -11,11 +11,13 @@ correction would absorb an error of the inner operator, this comparison sees
 it directly.  (The oracle's truncated iterates are pinned to the Krylov
 minimisation property of CG in the oracle's own pins.)
 
-Bars, element-wise max|x - x_o| / max|x_o| (norm-wise the same number is
-checked): FP32 4e-6 k, FP16 storage 6e-3 k, FP64 1e-12 k.  The factor k is a
-stated allowance for the growth of a rounding perturbation over k CG steps
-(alpha and beta are ratios of reductions of perturbed vectors); the printed
-values show the measured growth.
+Bars, element-wise max|x - x_o| / max|x_o| (the norm-wise error is held to
+the same bar), for k = 1, 2, 5: FP64 1e-13, FP32 1.5e-6 (12-real and 18-real
+links), FP16 storage 3e-3.  A rounding perturbation can grow over CG steps
+(alpha and beta are ratios of reductions of perturbed vectors); measured, it
+barely does over these k: FP32 2.6e-7 -> 4.5e-7 element-wise from k = 1 to 5
+at 16^3x32x16 (1.3e-7 -> 3.0e-7 norm-wise), FP16 8.2e-4 -> 1.0e-3, FP64 at
+most 6.3e-15 (printed by each case), so the bars leave a factor 3 or more.
 """
 import numpy as np
 import pytest
@@ -35,7 +37,7 @@ PROBS = {
 }
 # inner precision, link_compress (-1: the library's default, 12-real for an SU(3) field)
 PRECS = {"fp64": (0, -1), "fp32-12real": (1, 1), "fp32-18real": (1, 0), "fp16": (2, -1)}
-BAR = {0: 1e-12, 1: 4e-6, 2: 6e-3}
+BAR = {0: 1e-13, 1: 1.5e-6, 2: 3e-3}
 KS = (1, 2, 5)
 
 _cache = {}
@@ -75,5 +77,5 @@ def test_truncated_solve_matches_oracle_iterates(name, prec):
         assert rc == dwf.DWF_ENOCONV and st[0]["iters"] == k, st
         e_el, e_n = max_rel(x, ref[k]), rel(x, ref[k])
         print(f"[trunc]   k={k}: element-wise {e_el:.3e}, norm-wise {e_n:.3e}", flush=True)
-        assert e_el <= BAR[ip] * k, (k, e_el)
-        assert e_n <= BAR[ip] * k, (k, e_n)
+        assert e_el <= BAR[ip], (k, e_el)
+        assert e_n <= BAR[ip], (k, e_n)
