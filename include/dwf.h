@@ -202,6 +202,22 @@ int dwf_apply_dev(dwf_ctx *ctx, int op, int prec, const double *in_dev, double *
                   int nrhs, void *hip_stream);
 
 /*
+ * dwf_apply_dev_noalloc -- dwf_apply_dev for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same operators, kernels and results, with the
+ * eight half-field workspace taken from a static device array of the library
+ * (64 MiB, held by every GPU the library runs on until the process ends)
+ * instead of a per-context allocation.  Makes no hipMalloc / hipFree or other
+ * allocating call.  Arguments as dwf_apply_dev.  DWF_EINVAL when the
+ * workspace, nrhs x (V4 Ns / 2) x 8 half fields of the storage precision
+ * (FP64 1536, FP32 768, FP16 416 bytes per 5D half site and right-hand side,
+ * rounded up), exceeds the array.  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU race (serialize them).
+ */
+int dwf_apply_dev_noalloc(dwf_ctx *ctx, int op, int prec, const double *in_dev, double *out_dev,
+                          int nrhs, void *hip_stream);
+
+/*
  * dwf_solve -- solve D x = b (Eq. (5)) for nrhs right-hand sides.
  *   b, x  : host pointers, nrhs spinors in the host layout.  x is read as
  *           the initial guess when params->use_guess, and holds the

@@ -26,7 +26,7 @@ SU3_TOL = 1e-6
 EXPORTED = [
     "dwf_default_opts", "dwf_default_params", "dwf_create", "dwf_destroy", "dwf_apply", "dwf_apply_dev",
     "dwf_solve", "dwf_solve_dev", "dwf_submit", "dwf_submit_mass", "dwf_poll", "dwf_server_stats_get",
-    "dwf_time_kernels", "dwf_last_error", "dwf_version", "dwf_gauge_su3_deviation",
+    "dwf_time_kernels", "dwf_last_error", "dwf_version", "dwf_gauge_su3_deviation", "dwf_apply_dev_noalloc",
     "dwf_stream_copy",
 ]
 
@@ -106,6 +106,7 @@ def lib():
     L.dwf_destroy.restype = None
     L.dwf_apply.argtypes = [vp, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int]
     L.dwf_apply_dev.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+    L.dwf_apply_dev_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp]
     L.dwf_solve.argtypes = [vp, _dp, _dp, ctypes.c_int, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats)]
     L.dwf_solve_dev.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(SolveParams), ctypes.POINTER(SolveStats),
                                 vp]
@@ -281,6 +282,15 @@ class Context:
         check_device_spinors(out, self.dims, self.ns, nrhs, self.device)
         _check(lib().dwf_apply_dev(self._h, op, prec, ctypes.c_void_p(psi.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), nrhs, _stream_ptr(stream)))
+        return out
+
+    def apply_dev_noalloc(self, op, psi, out, prec=PREC_FP64, nrhs=1, stream=None):
+        """apply_dev with the workspace in the library's static device array
+        (dwf_apply_dev_noalloc: no device allocation)."""
+        check_device_spinors(psi, self.dims, self.ns, nrhs, self.device)
+        check_device_spinors(out, self.dims, self.ns, nrhs, self.device)
+        _check(lib().dwf_apply_dev_noalloc(self._h, op, prec, ctypes.c_void_p(psi.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), nrhs, _stream_ptr(stream)))
         return out
 
     # -- solves ----------------------------------------------------------

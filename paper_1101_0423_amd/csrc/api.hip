@@ -35,9 +35,29 @@ int DevBuf::alloc(size_t n) {
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && own) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    own = true;
+}
+
+void HalfField::sizes(int prec, long V5h, int nrhs, size_t* data_bytes, size_t* nrm_bytes) {
+    const int nblk = prec == DWF_PREC_FP64 ? 12 : prec == DWF_PREC_FP32 ? 6 : 3;
+    *data_bytes = (size_t)(((V5h * nblk + 255) / 256) * 256) * nrhs * 16;
+    *nrm_bytes = prec == DWF_PREC_FP16 ? (size_t)(((V5h + 1023) / 1024) * 1024) * nrhs * sizeof(float) : 0;
+}
+
+void HalfField::place(int prec_, long V5h, int Ns, int nrhs_, unsigned char* mem) {
+    prec = prec_;
+    nrhs = nrhs_;
+    ns = Ns;
+    const int nblk = prec == DWF_PREC_FP64 ? 12 : prec == DWF_PREC_FP32 ? 6 : 3;
+    rstride = ((V5h * nblk + 255) / 256) * 256;
+    nstride = ((V5h + 1023) / 1024) * 1024;
+    size_t db, nb;
+    sizes(prec, V5h, nrhs, &db, &nb);
+    data.view(mem, db);
+    if (nb) nrm.view(mem + db, nb);
 }
 
 int HalfField::alloc(int prec_, long V5h, int Ns, int nrhs_) {
@@ -350,9 +370,10 @@ int dwf_create(dwf_ctx** out, const double* gauge, const int dims[4], int Ns, do
     c->G64 = G > 0 ? std::max(1, G / 2) : std::min(32, std::max(1, 128 / Ns));
 
     DWF_HIP(hipSetDevice(c->device));
+    int rc = scratch_init(c->device);  // the allocation-free operator's workspace on this device
+    if (rc) return rc;
     DWF_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     DWF_HIP(hipStreamCreateWithFlags(&c->xfer, hipStreamNonBlocking));
-    int rc;
     {
         // share the resident links of an identical field
         const std::string key = gauge_key(gauge, dims, c->device);
@@ -458,6 +479,19 @@ int dwf_apply(dwf_ctx* c, int op, int prec, const double* in, double* out, int n
     HostIO io{in, out, nullptr, nullptr};
     if ((rc = c->ensure_stage(&io.stage_in, &io.stage_out))) return rc;
     return apply_op(c, op, prec, nullptr, nullptr, nrhs, c->stream, &io);
+}
+
+int dwf_apply_dev_noalloc(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs,
+                          void* stream) {
+    g_err.clear();
+    int rc = check_apply(c, op, prec, in_dev, out_dev, nrhs);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mtx);
+    DWF_HIP(hipSetDevice(c->device));
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    if ((rc = apply_op_noalloc(c, op, prec, in_dev, out_dev, nrhs, s))) return rc;
+    DWF_HIP(hipStreamSynchronize(s));
+    return DWF_OK;
 }
 
 int dwf_solve_dev(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params* params,

@@ -40,11 +40,18 @@ int fail(int code, const std::string& msg);
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool own = true;  // false: a view of memory owned elsewhere (never freed here)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     int alloc(size_t n);
+    void view(void* q, size_t n) {
+        release();
+        p = q;
+        bytes = n;
+        own = false;
+    }
     void release();
     template <class T>
     T* as() const { return (T*)p; }
@@ -82,6 +89,10 @@ struct HalfField {
     int nrhs = 0;
     DevBuf data, nrm;
     int alloc(int prec, long V5h, int Ns, int nrhs);
+    // bytes of the data and norm arrays of such a field (each a multiple of 256)
+    static void sizes(int prec, long V5h, int nrhs, size_t* data_bytes, size_t* nrm_bytes);
+    // the same field laid out in caller-owned device memory (data, then norms)
+    void place(int prec, long V5h, int Ns, int nrhs, unsigned char* mem);
     FD fd(int rhs0 = 0) const { return FD{data.as<double2>() + rhs0 * rstride, ns, rstride}; }
     FS fs(int rhs0 = 0) const { return FS{data.as<float4>() + rhs0 * rstride, ns, rstride}; }
     FH fh(int rhs0 = 0) const {
@@ -308,6 +319,12 @@ struct HostIO {
 // storage; in_dev / out_dev are device spinors unless hio is given.
 int apply_op(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs, hipStream_t s,
              const HostIO* hio = nullptr);
+// the same with the workspace in the library's static device scratch array
+// (ops.hip): no device allocation; DWF_EINVAL when it does not fit
+int apply_op_noalloc(dwf_ctx* c, int op, int prec, const double* in_dev, double* out_dev, int nrhs,
+                     hipStream_t s);
+// look up the scratch array's address on the current device (once per device)
+int scratch_init(int device);
 
 // the solver (solver.hip): nrhs right-hand sides, all with the context's mq;
 // b_dev / x_dev are device spinors unless hio is given (hio->in = b, hio->out = x)

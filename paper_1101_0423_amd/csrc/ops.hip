@@ -2,6 +2,8 @@
 // D_w (Eq. (2)), the hopping blocks D_w^EO / D_w^OE (Eq. (14)), M5 and M5^T
 // (Eq. (8)), the Schur complement C (Eq. (11)) and C^dag, C C^dag, and the
 // 5D operator D (Eq. (5)) and D^dag, each in FP64, FP32 or FP16 storage.
+#include <mutex>
+
 #include "dwf_ctx.h"
 
 namespace dwf {
@@ -153,7 +155,7 @@ struct Applier {
 };
 
 // The workspace of an application: NAPPLY half fields, kept by the context
-// per (precision, nrhs), or supplied by the caller (wsp).
+// per (precision, nrhs), or laid out in the static scratch array (wsp given).
 template <class Real, class F, class LF>
 int apply_impl(dwf_ctx* c, int op, int prec, LF e, LF o_, const double* in_dev, double* out_dev, int nrhs,
                hipStream_t s, const HostIO* hio, Workspace* wsp = nullptr) {
@@ -223,7 +225,35 @@ int dispatch(dwf_ctx* c, int op, int prec_flags, const double* in_dev, double* o
     }
 }
 
+// ---------------------------------------------------------------------------
+// The allocation-free form: its workspace is this file-scope device array, of
+// which every GPU the library runs on holds one copy for the life of the
+// process.  Host code never uses the array's name as an address (that is a
+// host-side stand-in); it uses the per-device address that hipGetSymbolAddress
+// returns, looked up once per device with that device current.  Calls that
+// overlap on one GPU share the array and race.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+int scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(DWF_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return DWF_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));  // the current device's copy
+    if (e != hipSuccess || !ptr)
+        return fail(DWF_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = (unsigned char*)ptr;
+    return DWF_OK;
+}
 
 // prec: storage precision, or-ed with a DWF_LINKS_* link storage (validated by
 // the caller); auto picks what the inner solver uses for this field
@@ -232,5 +262,31 @@ int apply_op(dwf_ctx* c, int op, int prec_flags, const double* in_dev, double* o
     return dispatch(c, op, prec_flags, in_dev, out_dev, nrhs, s, hio, nullptr);
 }
 
+int apply_op_noalloc(dwf_ctx* c, int op, int prec_flags, const double* in_dev, double* out_dev, int nrhs,
+                     hipStream_t s) {
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (c->device >= 0 && c->device < kMaxDevices) base = g_scratch_ptr[c->device];
+    }
+    if (!base) return fail(DWF_EDEVICE, "scratch array not set up on this device");
+    const int prec = prec_flags & 0xff;
+    size_t db, nb;
+    HalfField::sizes(prec, c->V5h, nrhs, &db, &nb);
+    const size_t need = (size_t)NAPPLY * (db + nb);
+    if (need > kScratchBytes)
+        return fail(DWF_EINVAL, "the allocation-free operator needs " + std::to_string(need) +
+                                    " bytes of workspace (nrhs x V4 x Ns / 2 x 8 half fields); its static scratch "
+                                    "array holds " + std::to_string(kScratchBytes));
+    // every field of the workspace is written in full before it is read, so
+    // nothing in the array has to start at zero
+    Workspace w;
+    w.nrhs = nrhs;
+    for (int i = 0; i < NAPPLY; ++i) {
+        w.fields.emplace_back(new HalfField);
+        w.fields.back()->place(prec, c->V5h, c->Ns, nrhs, base + (size_t)i * (db + nb));
+    }
+    return dispatch(c, op, prec_flags, in_dev, out_dev, nrhs, s, nullptr, &w);
+}
 
 }  // namespace dwf
