@@ -481,9 +481,11 @@ def main():
         n = 1 << 30
         src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
+        side = torch.cuda.Stream()  # the library never uses the legacy null stream
+        torch.cuda.synchronize()
         for nt in (False, True):
             for _ in range(3):
-                dwf.stream_copy(src, dst, nontemporal=nt)
+                dwf.stream_copy(src, dst, nontemporal=nt, stream=side.cuda_stream)
         del src, dst
         print(json.dumps(dict(mode="kernels", workload=wname, ms={k: ms[k] for k in ms},
                               bytes={k: by[k] for k in by}, copy_bytes_read=n, copy_bytes_written=n)), flush=True)

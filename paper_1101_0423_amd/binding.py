@@ -357,7 +357,8 @@ def poll(ticket, shape, timeout_us=0):
 def stream_copy(src, dst, nontemporal=False, stream=None):
     """Plain device copy src -> dst (torch tensors of equal byte size, a
     multiple of 16) with cached or non-temporal accesses (dwf_stream_copy):
-    the calibration reference of the memory counters."""
+    the calibration reference of the memory counters.  stream: a HIP stream
+    handle other than the legacy null stream (default: torch's current one)."""
     nb = src.numel() * src.element_size()
     if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
         raise ValueError("contiguous device tensors expected")
