@@ -73,6 +73,8 @@ def lib():
         L.orc_cgne_full.restype = ctypes.c_int
         L.orc_true_residual.argtypes = opargs
         L.orc_true_residual.restype = ctypes.c_double
+        L.orc_propagator.argtypes = opargs + [ctypes.c_double, ctypes.c_int, _ip, _dp]
+        L.orc_propagator.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -223,3 +225,27 @@ def true_residual(U, dims, ns, m0, mq, sigma, omega, b, x, bct=1.0):
     U, b, x = _f64(U), _f64(b), _f64(x)
     return lib().orc_true_residual(_p(U), _dims(dims), ns, m0, mq, _p(_f64(sigma)), _p(_f64(omega)),
                                    bct, _p(b), _p(x))
+
+
+def propagator(U, dims, ns, m0, mq, sigma, omega, eta, tol=1e-12, maxiter=100000, bct=1.0):
+    """4D quark propagator S eta = R D^-1 W eta (see orc_propagator) for a 4D
+    source eta [..][Lt][Lz][Ly][Lx][24] (one source, or several stacked in a
+    leading axis).  Returns (S eta, info dict of the last solve)."""
+    U, eta = _f64(U), _f64(eta)
+    lx, ly, lz, lt = dims
+    one = (lt, lz, ly, lx, 24)
+    many = eta.reshape((-1,) + one)
+    out = np.zeros_like(many)
+    info = {}
+    for k in range(many.shape[0]):
+        it = ctypes.c_int(0)
+        res = ctypes.c_double(0)
+        src = np.ascontiguousarray(many[k])
+        dst = np.zeros(one)
+        rc = lib().orc_propagator(_p(U), _dims(dims), ns, m0, mq, _p(_f64(sigma)), _p(_f64(omega)), bct,
+                                  _p(src), _p(dst), tol, maxiter, ctypes.byref(it), ctypes.byref(res))
+        if rc < 0:
+            raise ValueError("singular fifth-dimension matrix")
+        out[k] = dst
+        info = dict(converged=(rc == 0), iters=it.value, schur_res=res.value)
+    return out.reshape(eta.shape), info

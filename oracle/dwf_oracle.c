@@ -828,3 +828,75 @@ double orc_true_residual(const double *U, const int *dims, int Ns, double m0, do
     free(dx);
     return n > 0 ? sqrt(r / n) : sqrt(r);
 }
+
+/* ------------------------------------------------------------------------ */
+/* 4D valence-quark propagator from the 5D solve (Sec. 2.2: CG on the 5D      */
+/* system also gives the valence quark propagators; Sec. 5).  The paper does  */
+/* not spell out the 4D fields, so this follows from Eqs. (3)-(5):            */
+/*  - the quark mass enters only through the corner of L (Eq. (4)), and that  */
+/*    corner couples P_+ psi at s = Ns to s = 1 and P_- psi at s = 1 to        */
+/*    s = Ns.  Hence D(mq) = D(0) + kappa W R, kappa = mq / (2 m0), with      */
+/*      R psi = P_+ psi_Ns + P_- psi_1                    (5D -> 4D)          */
+/*      (W q)_1 = (1 - sigma_1 D_w) P_+ q,                                    */
+/*      (W q)_Ns = (1 - sigma_Ns D_w) P_- q, zero on the other slices.        */
+/*  - the 4D quark field is q = R psi (the walls, where the chiral modes of    */
+/*    the free operator sit for 0 < m0 < 2) and the source of a 4D spinor     */
+/*    eta is the 5D vector W eta, so that                                     */
+/*      S(mq) eta = R D(mq)^-1 W eta,                                         */
+/*    which makes the quark mass additive: S(mq)^-1 = S(0)^-1 + kappa.        */
+/* eta, out: 4D spinors [Lt][Lz][Ly][Lx][24].  The 5D solve is orc_solve's    */
+/* (Eq. (10) with CG on C C^dag) to tol.  Returns orc_solve's code.           */
+/* ------------------------------------------------------------------------ */
+
+int orc_propagator(const double *U, const int *dims, int Ns, double m0, double mq,
+                   const double *sigma, const double *omega, double bct,
+                   const double *eta, double *out, double tol, int maxiter,
+                   int *iters, double *schur_res)
+{
+    gamma_init();
+    lat_t l = lat_make(dims);
+    long N = l.V * Ns * 12;
+    const cplx *e = (const cplx *)eta;
+    cplx *q = (cplx *)out;
+    cplx *c = calloc(N, sizeof(cplx)), *dc = malloc(sizeof(cplx) * N);
+    cplx *b = malloc(sizeof(cplx) * N), *x = calloc(N, sizeof(cplx));
+    cplx Pp[4][4], Pm[4][4];
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) {
+            Pp[i][j] = 0.5 * ((i == j) + G[4][i][j]);
+            Pm[i][j] = 0.5 * ((i == j) - G[4][i][j]);
+        }
+    /* c: P_+ eta on slice 1, P_- eta on slice Ns (0-based 0 and Ns - 1) */
+    for (long n = 0; n < l.V; n++)
+        for (int i = 0; i < 4; i++)
+            for (int a = 0; a < 3; a++) {
+                cplx ap = 0, am = 0;
+                for (int j = 0; j < 4; j++) {
+                    ap += Pp[i][j] * e[n * 12 + 3 * j + a];
+                    am += Pm[i][j] * e[n * 12 + 3 * j + a];
+                }
+                c[(n * Ns + 0) * 12 + 3 * i + a] += ap;
+                c[(n * Ns + Ns - 1) * 12 + 3 * i + a] += am;
+            }
+    /* b = W eta = c - sigma_s D_w c (slice by slice) */
+    orc_dw(U, dims, Ns, m0, bct, (const double *)c, (double *)dc);
+    for (long n = 0; n < l.V; n++)
+        for (int s = 0; s < Ns; s++)
+            for (int k = 0; k < 12; k++) {
+                long i = (n * Ns + s) * 12 + k;
+                b[i] = c[i] - sigma[s] * dc[i];
+            }
+    int rc = orc_solve(U, dims, Ns, m0, mq, sigma, omega, bct, (const double *)b, (double *)x, tol, maxiter,
+                       iters, schur_res);
+    /* q = R x = P_+ x_Ns + P_- x_1 */
+    for (long n = 0; n < l.V; n++)
+        for (int i = 0; i < 4; i++)
+            for (int a = 0; a < 3; a++) {
+                cplx acc = 0;
+                for (int j = 0; j < 4; j++)
+                    acc += Pp[i][j] * x[(n * Ns + Ns - 1) * 12 + 3 * j + a] + Pm[i][j] * x[(n * Ns + 0) * 12 + 3 * j + a];
+                q[n * 12 + 3 * i + a] = acc;
+            }
+    free(c); free(dc); free(b); free(x);
+    return rc;
+}

@@ -39,8 +39,8 @@ MUTANTS = [
     ("M5 similarity transform with sqrt(omega) swapped",
      "M[s * Ns + t] = T[s * Ns + t] * sqrt(omega[t]) / sqrt(omega[s]);",
      "M[s * Ns + t] = T[s * Ns + t] * sqrt(omega[s]) / sqrt(omega[t]);"),
-    ("chiral projectors exchanged", "Pp[i][j] = 0.5 * ((i == j) + G[4][i][j]);",
-     "Pp[i][j] = 0.5 * ((i == j) - G[4][i][j]);"),
+    ("chiral projectors exchanged", "Pp[i][j] = 0.5 * ((i == j) + G[4][i][j]);   /* P_+ = (1 + gamma_5)/2 */",
+     "Pp[i][j] = 0.5 * ((i == j) - G[4][i][j]);   /* P_+ = (1 + gamma_5)/2 */"),
     ("Schur complement 1 + M5 D M5 D", "out[k] = odd ? in[k] - S->t2[k] : 0;\n    }\n}\n\n/* C^dag",
      "out[k] = odd ? in[k] + S->t2[k] : 0;\n    }\n}\n\n/* C^dag"),
     ("CGNE accumulates p instead of u", "for (long i = 0; i < N; i++) { y[i] += alpha * u[i]; r[i] -= alpha * q[i]; }",
@@ -57,6 +57,13 @@ MUTANTS = [
     ("CGNE direction update without beta (steepest descent)",
      "for (long i = 0; i < N; i++) p[i] = r[i] + beta * p[i];\n        rr = rr_new;\n        k++;\n    }\n    *iters = k;\n    *relres = bb",
      "for (long i = 0; i < N; i++) p[i] = r[i] + 0.0 * beta * p[i];\n        rr = rr_new;\n        k++;\n    }\n    *iters = k;\n    *relres = bb"),
+    ("propagator projects the walls exchanged (P_+ psi_1 + P_- psi_Ns)",
+     "acc += Pp[i][j] * x[(n * Ns + Ns - 1) * 12 + 3 * j + a] + Pm[i][j] * x[(n * Ns + 0) * 12 + 3 * j + a];",
+     "acc += Pp[i][j] * x[(n * Ns + 0) * 12 + 3 * j + a] + Pm[i][j] * x[(n * Ns + Ns - 1) * 12 + 3 * j + a];"),
+    ("propagator source without the (1 - sigma D_w) factor", "b[i] = c[i] - sigma[s] * dc[i];", "b[i] = c[i];"),
+    ("propagator source with the chiralities of the walls exchanged",
+     "c[(n * Ns + 0) * 12 + 3 * i + a] += ap;\n                c[(n * Ns + Ns - 1) * 12 + 3 * i + a] += am;",
+     "c[(n * Ns + 0) * 12 + 3 * i + a] += am;\n                c[(n * Ns + Ns - 1) * 12 + 3 * i + a] += ap;"),
 ]
 
 

@@ -505,3 +505,136 @@ def test_ccdag_solve_equals_dense_solve(kind):
     wc = inp.host_to_complex(w).ravel()
     assert np.all(wc[~odd] == 0)
     assert np.linalg.norm(wc[odd] - wd) / np.linalg.norm(wd) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# 4D propagator from the 5D solve (Sec. 2.2): S eta = R D^-1 W eta
+# ---------------------------------------------------------------------------
+
+
+def _chiral_proj():
+    g5m = np.diag([1.0, 1.0, -1.0, -1.0]).astype(complex)      # the chiral basis (reading 1)
+    return 0.5 * (np.eye(4) + g5m), 0.5 * (np.eye(4) - g5m), g5m
+
+
+def _prop_dense(a, dims):
+    """S as a dense 4D matrix (12 V4 x 12 V4 complex), column by column from
+    oracle.propagator on unit sources."""
+    import concurrent.futures
+    lx, ly, lz, lt = dims
+    n = lx * ly * lz * lt * 12
+    src = np.zeros((n, lt, lz, ly, lx, 24))
+    for k in range(n):
+        src.reshape(n, -1)[k, 2 * k] = 1.0
+
+    def run(k):  # the oracle's C code runs without the GIL: columns in parallel
+        out, info = oracle.propagator(*a, src[k], tol=1e-14)
+        assert info["converged"]
+        return inp.host_to_complex(out).reshape(-1)
+
+    with concurrent.futures.ThreadPoolExecutor(8) as ex:
+        cols = list(ex.map(run, range(n)))
+    return np.array(cols).T                                    # column k = S e_k
+
+
+def _prop_numpy(a, dims):
+    """The same matrix built independently: LAPACK inverse of the dense 5D
+    operator (Eq. (1), pinned above), with R and W written out here."""
+    U, _, ns, m0, mq, sigma, omega = a
+    lx, ly, lz, lt = dims
+    V = lx * ly * lz * lt
+    shape = (lt, lz, ly, lx, ns, 24)
+    D = dense_matrix(lambda v: oracle.d5(*a, v), shape)
+    Dw = dense_matrix(lambda v: oracle.dw(U, dims, ns, m0, v), shape)
+    Pp, Pm, _ = _chiral_proj()
+    n4, n5 = 12 * V, 12 * V * ns
+    C = np.zeros((n5, n4), complex)                            # c = P_+ eta on s = 1, P_- eta on s = Ns
+    Rm = np.zeros((n4, n5), complex)                           # R psi = P_+ psi_Ns + P_- psi_1
+    for x in range(V):
+        for i in range(4):
+            for j in range(4):
+                for col in range(3):
+                    r4 = 12 * x + 3 * i + col
+                    c4 = 12 * x + 3 * j + col
+                    C[12 * (x * ns + 0) + 3 * i + col, c4] += Pp[i, j]
+                    C[12 * (x * ns + ns - 1) + 3 * i + col, c4] += Pm[i, j]
+                    Rm[r4, 12 * (x * ns + ns - 1) + 3 * j + col] += Pp[i, j]
+                    Rm[r4, 12 * (x * ns + 0) + 3 * j + col] += Pm[i, j]
+    Sg = np.diag(np.tile(np.repeat(sigma, 12), V))
+    W = C - Sg @ Dw @ C                                        # (1 - sigma_s D_w) on the two walls
+    return Rm @ np.linalg.solve(D, W)
+
+
+@pytest.mark.parametrize("kind", ["odwf", "general"])
+def test_propagator_mass_enters_additively(kind):
+    """S(mq)^-1 = S(0)^-1 + kappa (kappa = mq / (2 m0)): the corner of L, the
+    only place mq enters (Eq. (4)), is kappa W R, so the Woodbury identity
+    gives R D(mq)^-1 W = (1 + kappa S(0))^-1 S(0), and two masses differ by
+    exactly the difference of their kappas.  Checked on dense matrices, and
+    the oracle's S against the same matrix built from a LAPACK inverse of the
+    dense 5D operator with R and W written out here."""
+    dims, ns, m0 = (2, 2, 2, 2), 4, 1.8
+    U = inp.gauge_field(dims, 0.3, seed=47)
+    sigma, omega = weights(kind, ns)
+    S = {mq: _prop_dense((U, dims, ns, m0, mq, sigma, omega), dims) for mq in (0.05, 0.3)}
+    Si = {mq: np.linalg.inv(S[mq]) for mq in S}
+    d = Si[0.3] - Si[0.05]
+    dk = (0.3 - 0.05) / (2 * m0)
+    assert np.max(abs(d - dk * np.eye(d.shape[0]))) < 1e-9 * np.max(abs(Si[0.05]))
+    Sn = _prop_numpy((U, dims, ns, m0, 0.05, sigma, omega), dims)
+    assert np.max(abs(S[0.05] - Sn)) < 1e-11 * np.max(abs(Sn))
+
+
+def test_propagator_gamma5_hermitian_for_shamir():
+    """With sigma = 0 and reflection-symmetric omega, D^dag = g5 R5 D g5 R5
+    (pinned above) and R g5 R5 = g5 W^dag, so S^dag = g5 S g5."""
+    dims, ns, m0, mq = (2, 2, 2, 2), 4, 1.8, 0.1
+    U = inp.gauge_field(dims, 0.3, seed=53)
+    w = np.random.default_rng(3).uniform(0.5, 1.5, ns)
+    a = (U, dims, ns, m0, mq, np.zeros(ns), 0.5 * (w + w[::-1]))
+    S = _prop_dense(a, dims)
+    _, _, g5m = _chiral_proj()
+    G5 = np.kron(np.eye(S.shape[0] // 12), np.kron(g5m, np.eye(3)))
+    assert np.max(abs(S.conj().T - G5 @ S @ G5)) < 1e-11 * np.max(abs(S))
+
+
+@pytest.mark.parametrize("kind", ["shamir", "odwf"])
+def test_propagator_free_field_momentum_space(kind):
+    """Unit links: a plane-wave source e^{ipx} chi gives e^{ipx} S(p) chi with
+    S(p) = R D(p)^-1 W(p) built from the 4Ns x 4Ns momentum block
+    D(p) = D_w(p)(omega + sigma L) + (1 - L), D_w(p) = (4 - m0 - sum cos p)
+    + i sum gamma sin p (the closed form pinned for D_w above), written out
+    here with the chiral gamma matrices."""
+    dims, ns, m0, mq = (4, 2, 2, 6), 5, 1.7, 0.08
+    lx, ly, lz, lt = dims
+    sigma, omega = weights(kind, ns)
+    U = inp.unit_gauge(dims)
+    kappa = mq / (2 * m0)
+    g = [oracle.gamma(m) for m in range(4)]
+    Pp, Pm, _ = _chiral_proj()
+    Lp = np.diag(np.ones(ns - 1), -1)
+    Lp[0, ns - 1] = -kappa
+    Lm = Lp.T
+    t, z, y, x = np.meshgrid(range(lt), range(lz), range(ly), range(lx), indexing="ij")
+    rng = np.random.default_rng(9)
+    for n in [(1, 0, 1, 2), (0, 1, 0, 5), (3, 1, 1, 0)]:
+        p = [2 * np.pi * n[k] / dims[k] for k in range(4)]
+        Dwp = (4 - m0 - sum(np.cos(pm) for pm in p)) * np.eye(4) + 1j * sum(g[m] * np.sin(p[m]) for m in range(4))
+        Lmat = np.kron(Lp, Pp) + np.kron(Lm, Pm)                # [s, spin] x [s', spin']
+        Om, Sg = np.kron(np.diag(omega), np.eye(4)), np.kron(np.diag(sigma), np.eye(4))
+        Dp = np.kron(np.eye(ns), Dwp) @ (Om + Sg @ Lmat) + np.eye(4 * ns) - Lmat
+        Wp = np.zeros((4 * ns, 4), complex)
+        Wp[0:4] = (np.eye(4) - sigma[0] * Dwp) @ Pp
+        Wp[4 * (ns - 1):] = (np.eye(4) - sigma[ns - 1] * Dwp) @ Pm
+        Rp = np.zeros((4, 4 * ns), complex)
+        Rp[:, 4 * (ns - 1):] = Pp
+        Rp[:, 0:4] += Pm
+        Sp = Rp @ np.linalg.solve(Dp, Wp)
+        chi = rng.normal(size=(4, 3)) + 1j * rng.normal(size=(4, 3))
+        phase = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))[..., None, None]
+        eta = inp.complex_to_host((phase * chi).reshape(lt, lz, ly, lx, 12))
+        out, info = oracle.propagator(U, dims, ns, m0, mq, sigma, omega, eta, tol=1e-14)
+        assert info["converged"]
+        got = inp.host_to_complex(out).reshape(lt, lz, ly, lx, 4, 3)
+        exp = phase * (Sp @ chi)
+        assert np.max(abs(got - exp)) < 1e-11 * np.max(abs(exp)), n
