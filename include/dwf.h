@@ -238,6 +238,36 @@ int dwf_solve_dev(dwf_ctx *ctx, const double *b_dev, double *x_dev, int nrhs,
                   const dwf_solve_params *params, dwf_solve_stats *stats, void *hip_stream);
 
 /*
+ * dwf_propagator -- 4D valence-quark propagators from the 5D solve (the use of
+ * the CG for valence quark propagators, Secs. 2.2 and 5).  The quark mass
+ * enters D only through the corner of L (Eq. (4)), which couples the +
+ * chirality at s = Ns to s = 1 and the - chirality at s = 1 to s = Ns:
+ * D(mq) = D(0) + kappa W R, kappa = mq / (2 m0), with
+ *     R psi      = P_+ psi_Ns + P_- psi_1          (the 4D quark field, 5D -> 4D)
+ *     (W eta)_1  = (1 - sigma_1 D_w) P_+ eta,
+ *     (W eta)_Ns = (1 - sigma_Ns D_w) P_- eta      (the 5D source of a 4D spinor).
+ * For each of nsrc 4D sources eta_k it solves D x = W eta_k (as dwf_solve,
+ * all sources in one batch, FP64 true residual of the 5D system <= tol) and
+ * returns out_k = R x.  With this choice the mass is additive:
+ * S(mq)^-1 = S(0)^-1 + kappa (S eta = R D^-1 W eta).  No contact term is
+ * subtracted (the paper defines none).
+ *   eta, out : host pointers, nsrc 4D spinors [Lt][Lz][Ly][Lx][24] each (the
+ *              spinor layout of this header without the s index).
+ *   params   : as dwf_solve (system must be DWF_SYSTEM_D; use_guess ignored).
+ *   stats    : NULL or nsrc entries, those of the 5D solves.
+ * The host form goes through the context's staging buffer in groups of up to
+ * Ns sources; the 5D work buffers (three 5D spinors per source) are kept by
+ * the context.  Returns DWF_OK, DWF_ENOCONV (out holds the best iterate's
+ * projection) or an error.
+ */
+int dwf_propagator(dwf_ctx *ctx, const double *eta, double *out, int nsrc,
+                   const dwf_solve_params *params, dwf_solve_stats *stats);
+
+/* Same, with device pointers (FP64, the 4D layout above) on a HIP stream. */
+int dwf_propagator_dev(dwf_ctx *ctx, const double *eta_dev, double *out_dev, int nsrc,
+                       const dwf_solve_params *params, dwf_solve_stats *stats, void *hip_stream);
+
+/*
  * dwf_submit -- enqueue one solve request on the context's device server
  * (continuous batching: requests on the same gauge field and fifth-dimension
  * weights are solved together in the multi-RHS kernels, with their own mq;

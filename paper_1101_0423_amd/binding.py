@@ -27,7 +27,7 @@ EXPORTED = [
     "dwf_default_opts", "dwf_default_params", "dwf_create", "dwf_destroy", "dwf_apply", "dwf_apply_dev",
     "dwf_solve", "dwf_solve_dev", "dwf_submit", "dwf_submit_mass", "dwf_poll", "dwf_server_stats_get",
     "dwf_time_kernels", "dwf_last_error", "dwf_version", "dwf_gauge_su3_deviation", "dwf_apply_dev_noalloc",
-    "dwf_stream_copy",
+    "dwf_stream_copy", "dwf_propagator", "dwf_propagator_dev",
 ]
 
 
@@ -118,6 +118,10 @@ def lib():
     L.dwf_time_kernels.argtypes = [vp, ctypes.POINTER(SolveParams), ctypes.c_int, ctypes.c_int, _dp, _dp]
     L.dwf_gauge_su3_deviation.argtypes = [_dp, ctypes.POINTER(ctypes.c_int), _dp]
     L.dwf_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp]
+    L.dwf_propagator.argtypes = [vp, _dp, _dp, ctypes.c_int, ctypes.POINTER(SolveParams),
+                                 ctypes.POINTER(SolveStats)]
+    L.dwf_propagator_dev.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(SolveParams),
+                                     ctypes.POINTER(SolveStats), vp]
     L.dwf_last_error.restype = ctypes.c_char_p
     L.dwf_version.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -319,6 +323,44 @@ class Context:
                                         nrhs, ctypes.byref(p), st, _stream_ptr(stream)),
                     ok=(DWF_OK, DWF_ENOCONV))
         return [s.as_dict() for s in st], rc
+
+    def spinor4_shape(self, nsrc=None):
+        lx, ly, lz, lt = self.dims
+        s = (lt, lz, ly, lx, 24)
+        return s if nsrc is None else (int(nsrc),) + s
+
+    def propagator(self, eta, params=None, **kw):
+        """4D propagators R D^-1 W eta for host sources [nsrc?][Lt][Lz][Ly][Lx][24]
+        (dwf_propagator); returns (out, [stats dict per source], status)."""
+        eta = _f64(eta)
+        one = self.spinor4_shape()
+        if eta.shape == one:
+            nsrc = 1
+        elif eta.ndim == 6 and eta.shape[1:] == one and eta.shape[0] >= 1:
+            nsrc = eta.shape[0]
+        else:
+            raise ValueError(f"source array of shape {eta.shape}; expected {one} or (nsrc,) + {one}")
+        p = params if params is not None else default_params(**kw)
+        out = np.zeros_like(eta)
+        st = (SolveStats * nsrc)()
+        rc = _check(lib().dwf_propagator(self._h, _ptr(eta), _ptr(out), nsrc, ctypes.byref(p), st),
+                    ok=(DWF_OK, DWF_ENOCONV))
+        return out, [x.as_dict() for x in st], rc
+
+    def propagator_dev(self, eta, out, nsrc=1, params=None, stream=None, **kw):
+        """Device tensors (torch float64, contiguous, nsrc 4D spinors)."""
+        import torch
+        n = int(nsrc) * int(np.prod(self.spinor4_shape()))
+        for t in (eta, out):
+            if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda and
+                    t.device.index == self.device and t.is_contiguous() and t.numel() == n):
+                raise ValueError(f"expected contiguous float64 tensors of {n} elements on cuda:{self.device}")
+        p = params if params is not None else default_params(**kw)
+        st = (SolveStats * nsrc)()
+        rc = _check(lib().dwf_propagator_dev(self._h, ctypes.c_void_p(eta.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()), nsrc, ctypes.byref(p), st,
+                                             _stream_ptr(stream)), ok=(DWF_OK, DWF_ENOCONV))
+        return [x.as_dict() for x in st], rc
 
     def time_kernels(self, params=None, nrhs=1, launches=20, **kw):
         """Average ms and algorithmic bytes of the inner kernels E, A, B, C, D."""

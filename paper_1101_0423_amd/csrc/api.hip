@@ -521,6 +521,52 @@ int dwf_time_kernels(dwf_ctx* c, const dwf_solve_params* params, int nrhs, int l
     return time_inner_kernels(c, p, nrhs, launches, ms, bytes);
 }
 
+int dwf_propagator_dev(dwf_ctx* c, const double* eta_dev, double* out_dev, int nsrc,
+                       const dwf_solve_params* params, dwf_solve_stats* stats, void* stream) {
+    g_err.clear();
+    dwf_solve_params p;
+    int rc = check_solve(c, eta_dev, out_dev, nsrc, params, &p);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mtx);
+    DWF_HIP(hipSetDevice(c->device));
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    return propagator(c, eta_dev, out_dev, nsrc, p, stats, s);
+}
+
+int dwf_propagator(dwf_ctx* c, const double* eta, double* out, int nsrc, const dwf_solve_params* params,
+                   dwf_solve_stats* stats) {
+    g_err.clear();
+    dwf_solve_params p;
+    int rc = check_solve(c, eta, out, nsrc, params, &p);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mtx);
+    DWF_HIP(hipSetDevice(c->device));
+    // A 4D spinor is Ns times smaller than a 5D one: each half of the
+    // context's two-spinor staging buffer holds Ns sources, so the sources go
+    // through in groups of up to Ns (each group one batched solve; a source's
+    // result does not depend on the others in its group)
+    const size_t n4 = (size_t)c->V4 * 24;
+    double *si, *so;
+    if ((rc = c->ensure_stage(&si, &so))) return rc;
+    hipStream_t s = c->stream;
+    int status = DWF_OK;
+    std::string msg;
+    for (int k0 = 0; k0 < nsrc; k0 += c->Ns) {
+        const int n = std::min(c->Ns, nsrc - k0);
+        DWF_HIP(hipMemcpyAsync(si, eta + k0 * n4, n * n4 * sizeof(double), hipMemcpyHostToDevice, s));
+        rc = propagator(c, si, so, n, p, stats ? stats + k0 : nullptr, s);
+        if (rc != DWF_OK && rc != DWF_ENOCONV) return rc;
+        if (rc) {
+            status = rc;
+            msg = dwf_last_error();
+        }
+        DWF_HIP(hipMemcpyAsync(out + k0 * n4, so, n * n4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        DWF_HIP(hipStreamSynchronize(s));
+    }
+    if (status) fail(status, msg);
+    return status;
+}
+
 int dwf_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, int nontemporal, int device,
                     void* stream) {
     g_err.clear();

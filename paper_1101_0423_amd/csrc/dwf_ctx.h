@@ -200,6 +200,7 @@ struct dwf_ctx {
     double su3_dev = 0;    // su3_deviation of the field
     bool su3 = true;       // su3_dev <= DWF_SU3_TOL: 12-real links are exact
     dwf::DevBuf stage;     // host-pointer forms: one spinor in, one out (FP64, host layout)
+    dwf::DevBuf prop_ws;   // propagator: wall source, 5D source and 5D solution per source
 
     dwf::Geom geom(int out_parity, bool fp64) const;
     const dwf::TableSet* table_set(double mq_val, int* rc);
@@ -330,6 +331,11 @@ int scratch_init(int device);
 // b_dev / x_dev are device spinors unless hio is given (hio->in = b, hio->out = x)
 int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_solve_params& p,
           dwf_solve_stats* stats, hipStream_t s, const HostIO* hio = nullptr);
+
+// 4D propagators (prop.hip): out = R D^-1 W eta for nsrc 4D sources, device
+// pointers in the host layouts
+int propagator(dwf_ctx* c, const double* eta_dev, double* out_dev, int nsrc, const dwf_solve_params& p,
+               dwf_solve_stats* stats, hipStream_t s);
 
 // the request server (server.hip): stop and forget the context's engines
 void server_detach(dwf_ctx* c);
