@@ -152,6 +152,27 @@ typedef struct dwf_solve_stats {
     double hbm_gbytes;       /* algorithmic HBM bytes moved / 1e9                         */
 } dwf_solve_stats;
 
+/*
+ * dwf_odwf_weights -- the weights omega_s of optimal domain-wall fermions (Sec.
+ * 2.1: sigma = omega, with omega_s fixed for optimal chiral symmetry; the
+ * paper cites the formula without giving it, so it is derived here).  With
+ * sigma = omega the 4D operator on the walls depends on the weights only
+ * through the transfer product
+ *     Pi(lam) = prod_s (1 - omega_s lam) / (1 + omega_s lam)
+ * over the spectrum of H = gamma_5 D_w, and is chirally exact where Pi = 0.
+ * The weights returned minimise max |Pi| for lam in [lambda_min, lambda_max]
+ * (Zolotarev's third problem):
+ *     omega_s = dn((2s - 1) K / (2 Ns), k) / lambda_min,   s = 1 .. Ns,
+ *     k = sqrt(1 - (lambda_min / lambda_max)^2),  K = K(k),
+ * with the error equioscillating at Ns + 1 points of the interval.  omega_1
+ * ~ 1 / lambda_min falls to omega_Ns ~ 1 / lambda_max (the 4D operator does
+ * not depend on their order along s).  The caller supplies bounds of |H|'s
+ * spectrum; pass omega as both sigma and omega to dwf_create.  Host only.
+ *   omega : Ns doubles, written.
+ * Errors: DWF_EINVAL unless Ns >= 1 and 0 < lambda_min <= lambda_max < inf.
+ */
+int dwf_odwf_weights(int Ns, double lambda_min, double lambda_max, double *omega);
+
 /* Fill defaults. */
 void dwf_default_opts(dwf_opts *opts);
 void dwf_default_params(dwf_solve_params *params);

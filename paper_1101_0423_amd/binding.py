@@ -27,7 +27,7 @@ EXPORTED = [
     "dwf_default_opts", "dwf_default_params", "dwf_create", "dwf_destroy", "dwf_apply", "dwf_apply_dev",
     "dwf_solve", "dwf_solve_dev", "dwf_submit", "dwf_submit_mass", "dwf_poll", "dwf_server_stats_get",
     "dwf_time_kernels", "dwf_last_error", "dwf_version", "dwf_gauge_su3_deviation", "dwf_apply_dev_noalloc",
-    "dwf_stream_copy", "dwf_propagator", "dwf_propagator_dev",
+    "dwf_stream_copy", "dwf_propagator", "dwf_propagator_dev", "dwf_odwf_weights",
 ]
 
 
@@ -118,6 +118,7 @@ def lib():
     L.dwf_time_kernels.argtypes = [vp, ctypes.POINTER(SolveParams), ctypes.c_int, ctypes.c_int, _dp, _dp]
     L.dwf_gauge_su3_deviation.argtypes = [_dp, ctypes.POINTER(ctypes.c_int), _dp]
     L.dwf_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp]
+    L.dwf_odwf_weights.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp]
     L.dwf_propagator.argtypes = [vp, _dp, _dp, ctypes.c_int, ctypes.POINTER(SolveParams),
                                  ctypes.POINTER(SolveStats)]
     L.dwf_propagator_dev.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(SolveParams),
@@ -408,6 +409,14 @@ def stream_copy(src, dst, nontemporal=False, stream=None):
         raise ValueError("equal sizes, a multiple of 16 bytes, expected")
     _check(lib().dwf_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nb,
                                  int(bool(nontemporal)), src.device.index, _stream_ptr(stream)))
+
+
+def odwf_weights(ns, lambda_min, lambda_max):
+    """The optimal domain-wall weights omega_s for |spec(gamma_5 D_w)| in
+    [lambda_min, lambda_max] (dwf_odwf_weights); use them as sigma and omega."""
+    out = np.zeros(int(ns))
+    _check(lib().dwf_odwf_weights(int(ns), float(lambda_min), float(lambda_max), _ptr(out)))
+    return out
 
 
 def server_stats(reset=False):

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.environ.get("DWF_OBJ_DIR", os.path.join(HERE, "_build"))
 LIB = os.environ.get("DWF_LIB_OUT", os.path.join(HERE, "libdwf.so"))
-SOURCES = ["api.hip", "layout.hip", "ops.hip", "solver.hip", "server.hip", "prop.hip"]
+SOURCES = ["api.hip", "layout.hip", "ops.hip", "solver.hip", "server.hip", "prop.hip", "odwf.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -237,3 +237,20 @@ def test_full_size_batched_point_sources():
     print(f"forward error estimate {err:.3e} (|x| {np.linalg.norm(x0):.6e} vs oracle {g['norm_x']:.6e})", flush=True)
     assert err <= TOL_FWD, err
     assert abs(np.linalg.norm(x0) / g["norm_x"] - 1) <= TOL_FWD
+
+
+def test_solve_with_optimal_domain_wall_weights():
+    """sigma = omega = the optimal weights of dwf_odwf_weights (Ns = 12,
+    |spec(H)| in [0.1, 5]): the operator takes any weights, and the solve meets
+    the same bars with the oracle's operator and solution."""
+    import paper_1101_0423_amd as dwf
+    w = dwf.odwf_weights(12, 0.1, 5.0)
+    P = Problem((8, 4, 4, 8), 12, 1.8, 0.03, w, w, 0.4, 45, 46)
+    print(f"[solve] optimal weights {np.round(w, 3)}", flush=True)
+    c = P.context()
+    try:
+        x, st, rc = c.solve(P.b, inner_prec=1)
+        assert rc == dwf.DWF_OK, st
+        check(P, x, oracle_solution(P, "odwf-optimal"))
+    finally:
+        c.close()

@@ -638,3 +638,75 @@ def test_propagator_free_field_momentum_space(kind):
         got = inp.host_to_complex(out).reshape(lt, lz, ly, lx, 4, 3)
         exp = phase * (Sp @ chi)
         assert np.max(abs(got - exp)) < 1e-11 * np.max(abs(exp)), n
+
+
+# ---------------------------------------------------------------------------
+# optimal domain-wall weights (Sec. 2.1): the transfer product and its minimax
+# ---------------------------------------------------------------------------
+
+
+def test_odwf_walls_see_the_transfer_product():
+    """With sigma = omega the 4D propagator at mq = 0 satisfies
+    S(0)^-1 = (1 + V)/(1 - V), V = g5 (1 - Pi(H))/(1 + Pi(H)),
+    Pi(H) = prod_s (1 - omega_s H)/(1 + omega_s H), H = g5 D_w: the weights
+    reach the 4D operator only through Pi on the spectrum of H (dense
+    matrices; H diagonalised by LAPACK)."""
+    dims, ns, m0 = (2, 2, 2, 2), 4, 1.8
+    U = inp.gauge_field(dims, 0.3, seed=59)
+    w = np.random.default_rng(1).uniform(0.5, 1.5, ns)
+    S0 = _prop_dense((U, dims, ns, m0, 0.0, w, w), dims)
+    Dw = dense_matrix(lambda v: oracle.dw(U, dims, 1, m0, v), (2, 2, 2, 2, 1, 24))
+    n = Dw.shape[0]
+    G5 = np.kron(np.eye(n // 12), np.kron(np.diag([1.0, 1.0, -1.0, -1.0]), np.eye(3)))
+    lam, Q = np.linalg.eigh(G5 @ Dw)
+    Pi = np.prod([(1 - o * lam) / (1 + o * lam) for o in w], axis=0)
+    V = G5 @ (Q @ np.diag((1 - Pi) / (1 + Pi)) @ Q.conj().T)
+    A = (np.eye(n) + V) @ np.linalg.inv(np.eye(n) - V)
+    Si = np.linalg.inv(S0)
+    assert np.max(abs(Si - A)) < 1e-10 * np.max(abs(A))
+
+
+def _zol_extrema(omega, a, b, n=400001):
+    """Signs and magnitudes of the local extrema of Pi on a dense log grid,
+    with both ends."""
+    from oracle import zolotarev
+    t = np.exp(np.linspace(np.log(a), np.log(b), n))
+    E = zolotarev.transfer_product(omega, t)
+    idx = [0] + [i for i in range(1, n - 1) if abs(E[i]) >= abs(E[i - 1]) and abs(E[i]) >= abs(E[i + 1])
+                 and abs(E[i]) > 0] + [n - 1]
+    return E[idx], np.max(np.abs(E))
+
+
+@pytest.mark.parametrize("ns", [1, 2, 5, 8, 16])
+def test_optimal_weights_minimax(ns):
+    """The oracle's optimal weights (a Remez exchange on the minimax of
+    |Pi| over [a, b]) against what fixes them without the exchange: for Ns = 1
+    the closed form omega = 1/sqrt(ab) (|Pi| equal at both ends); for every Ns
+    the Chebyshev alternation that characterises the unique minimax solution
+    (Ns + 1 extrema of equal size and alternating sign, found on a dense grid
+    independent of the exchange's own search); the symmetry of the problem
+    under lam -> ab / lam (the zeros map onto themselves); no nearby weights do
+    better; and the classical closed form of Zolotarev's third problem,
+    zeros b dn((2j - 1) K / (2 Ns), k), k = sqrt(1 - (a/b)^2), evaluated with
+    scipy's elliptic functions."""
+    import scipy.special as sps
+
+    from oracle import zolotarev
+    a, b = 0.04, 5.5
+    w = zolotarev.optimal_omega(ns, a, b)
+    if ns == 1:
+        assert abs(w[0] - 1 / np.sqrt(a * b)) < 1e-13 * w[0]
+    ext, emax = _zol_extrema(w, a, b)
+    assert len(ext) == ns + 1
+    assert np.all(np.sign(ext[1:]) == -np.sign(ext[:-1]))
+    assert np.max(np.abs(np.abs(ext) - emax)) < 1e-8 * emax
+    p = np.sort(1 / w)
+    assert np.max(np.abs(np.sort(a * b / p) - p) / p) < 1e-12
+    rng = np.random.default_rng(ns)
+    for _ in range(5):
+        wp = w * np.exp(1e-3 * rng.standard_normal(ns))
+        assert _zol_extrema(wp, a, b)[1] > emax
+    k = np.sqrt(1 - (a / b) ** 2)
+    u = (2 * np.arange(1, ns + 1) - 1) * sps.ellipk(k * k) / (2 * ns)
+    dn = sps.ellipj(u, k * k)[2]
+    assert np.max(np.abs(np.sort(b * dn) - p) / p) < 1e-11
