@@ -14,6 +14,14 @@
 // as large as the budget allows (at most kMaxBatch).  A request whose lane
 // does not exist and does not fit waits; idle lanes give their memory back
 // while requests wait for memory.
+//
+// Scheduling: a lane whose lattice fills the GPU by itself ("large": at
+// least kLargeV5h half 5D sites) runs only while it holds one of the
+// kLargeLanes oldest requests among the large lanes with work; the others wait
+// for their turn.  Large solves therefore run in arrival order at the full
+// speed of the device instead of sharing it, while lanes of small lattices,
+// whose iterations are bound by launch latency rather than bandwidth, run
+// beside them at any time.
 #include <math.h>
 #include <string.h>
 
@@ -34,6 +42,22 @@ constexpr int kMaxBatch = 8;
 // graph replays (of 4 iterations) between scheduling rounds of a lane, so that
 // a new request waits at most this long for its slot
 constexpr int kReplayCap = 16;
+// lanes of at least this many half 5D sites (16^3 x 32 x 8) fill the GPU alone
+constexpr long kLargeV5h = 1L << 19;
+// large lanes that may run at once (DWF_SERVE_LARGE_LANES overrides).  On the
+// served stream of four fields (200 requests at 0.8 of the plain capacity, and
+// 60 at once), 1 serialises too much (p99 9.9 s, fewer solves/s than a FIFO
+// of plain solves), no limit lets large solves share the GPU so long that p99
+// exceeds the FIFO's (8.7 s vs 8.3 s), and 2-3 beat the FIFO on p50, p99 and
+// solves/s alike
+int large_lanes() {
+    static const int n = [] {
+        const char* e = getenv("DWF_SERVE_LARGE_LANES");
+        const int v = e ? atoi(e) : 3;
+        return v > 0 ? v : 1;
+    }();
+    return n;
+}
 
 struct Request {
     uint64_t ticket = 0;
@@ -61,6 +85,7 @@ struct Lane {
     std::vector<ReqP> slot;
     std::condition_variable cv;
     std::thread th;
+    bool large = false;    // V5h >= kLargeV5h: runs in arrival order with the other large lanes
     bool cancel = false;   // fail everything and exit (context destroyed, shutdown)
     bool closing = false;  // idle and giving its memory back: takes no new requests
     bool exited = false;
@@ -73,6 +98,7 @@ struct Server {
     std::map<std::string, std::unique_ptr<Lane>> lanes;
     std::vector<std::unique_ptr<Lane>> dead;  // exited, not yet joined
     std::condition_variable cv_exit;          // a lane thread has exited
+    std::condition_variable cv_turn;          // the order of the large lanes may have changed
     std::deque<ReqP> waiting;  // their lane does not exist and does not fit yet
     uint64_t next_ticket = 1;
     size_t used = 0;
@@ -112,6 +138,38 @@ void service_end(Server& S) {
 }
 
 void lane_main(Lane* L);
+
+// Submission time of the oldest request a lane holds (in a slot or queued);
+// false if it holds none (lock held).
+bool oldest_request(const Lane* L, Clock::time_point* t) {
+    bool any = false;
+    for (auto& q : L->slot)
+        if (q && (!any || q->t_submit < *t)) {
+            *t = q->t_submit;
+            any = true;
+        }
+    for (auto& q : L->queue)
+        if (!any || q->t_submit < *t) {
+            *t = q->t_submit;
+            any = true;
+        }
+    return any;
+}
+
+// A large lane's turn: its oldest request is among the large_lanes() oldest
+// of the large lanes that hold requests (lock held).
+bool large_turn(const Server& S, const Lane* L) {
+    Clock::time_point mine;
+    if (!oldest_request(L, &mine)) return true;
+    int older = 0;
+    for (auto& kv : S.lanes) {
+        const Lane* o = kv.second.get();
+        if (o == L || !o->large || o->cancel || o->closing || o->exited) continue;
+        Clock::time_point t;
+        if (oldest_request(o, &t) && (t < mine || (t == mine && o < L))) ++older;
+    }
+    return older < large_lanes();
+}
 
 // Join and drop the lanes whose thread has ended (lock held).  The lane of
 // the calling thread goes to the graveyard and is joined later by another.
@@ -177,6 +235,7 @@ bool route(Server& S, const ReqP& q, bool front) {
     L->K = K;
     L->bytes = stage + engine_bytes(q->ctx, q->p.inner_prec, K);
     L->slot.assign(K, nullptr);
+    L->large = q->ctx->V5h >= kLargeV5h;
     L->queue.push_back(q);
     S.used += L->bytes;
     Lane* raw = L.get();
@@ -260,8 +319,12 @@ void lane_main(Lane* L) {
             for (auto& a : adm) std::vector<double>().swap(a.second->b);  // b is on the device now
         }
         {
-            std::lock_guard<std::mutex> lk(S.mu);
+            std::unique_lock<std::mutex> lk(S.mu);
             S.peak_batch = std::max<int64_t>(S.peak_batch, eng->busy());
+            // a large lane waits for its turn (re-checked at least every 2 ms)
+            while (L->large && !L->cancel && !large_turn(S, L))
+                S.cv_turn.wait_for(lk, std::chrono::milliseconds(2));
+            if (L->cancel) break;
         }
         if ((rc = eng->tick())) break;
         for (int r = 0; r < L->K && !rc; ++r) {
@@ -292,6 +355,7 @@ void lane_main(Lane* L) {
             S.lat.push_back(std::chrono::duration<double>(Clock::now() - q->t_submit).count());
             service_end(S);
             complete(S, q, res.status, res.status == DWF_OK ? "" : "solve did not reach the requested tolerance");
+            S.cv_turn.notify_all();
         }
     }
     if (rc && why.empty()) why = dwf_last_error();
@@ -312,6 +376,7 @@ void lane_main(Lane* L) {
     S.used -= L->bytes;
     L->exited = true;
     S.cv_exit.notify_all();
+    S.cv_turn.notify_all();
     // hand the memory to waiting requests; this lane is joined by the next
     // caller that reaps (never by itself)
     dispatch_waiting(S);
@@ -324,6 +389,7 @@ void cancel_lanes(Server& S, std::unique_lock<std::mutex>& lk, Pred pred) {
         if (pred(kv.second.get())) {
             kv.second->cancel = true;
             kv.second->cv.notify_all();
+            S.cv_turn.notify_all();
         }
     S.cv_exit.wait(lk, [&] {
         for (auto& kv : S.lanes)

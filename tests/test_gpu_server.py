@@ -193,3 +193,32 @@ def test_submit_rejects_bad_requests():
         assert ei.value.code == dwf.DWF_EINVAL
     finally:
         c.close()
+
+
+def test_request_during_lane_release_is_served():
+    """A budget that holds one lane: a request for operator A arrives just as
+    A's idle lane gives its memory back to a waiting request for operator B.
+    It must wait for a new lane and be served, not fail as if its context had
+    been destroyed."""
+    import paper_1101_0423_amd as dwf
+    V5h = 4 ** 4 // 2 * SMALL.ns
+    per_slot = (8 * V5h * 192 + 6 * V5h * 96) * 1.1 + 64 * 1024
+    staging = 4 ** 4 * SMALL.ns * 24 * 8
+    budget = int(1.6 * per_slot + staging)
+    ca = ctx_mass(SMALL, 0.05, hbm_budget_bytes=budget)
+    cb = ctx_mass(SMALL, 0.1, hbm_budget_bytes=budget)
+    try:
+        for k in range(4):
+            ba, bb, ba2 = rhs(SMALL, 600 + k), rhs(SMALL, 610 + k), rhs(SMALL, 620 + k)
+            ta = ca.submit(ba)
+            tb = cb.submit(bb)                      # waits for A's lane to go
+            rc, x, st = wait(ta, ca.spinor_shape())
+            assert rc == dwf.DWF_OK, st
+            ta2 = ca.submit(ba2)                    # A's lane is idle and releasing now
+            for mq, b, t in ((0.1, bb, tb), (0.05, ba2, ta2)):
+                rc, x, st = wait(t, ca.spinor_shape())
+                assert rc == dwf.DWF_OK, st
+                assert true_res(SMALL, mq, b, x) <= TOL_RES
+    finally:
+        ca.close()
+        cb.close()
