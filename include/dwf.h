@@ -133,6 +133,11 @@ typedef struct dwf_solve_params {
                                 of the HMC force, Sec. 2.1): the even sites of b are
                                 ignored and those of w are zero; true_residual is then
                                 ||b_o - C C^dag w|| / ||b_o||                               */
+    int tile;                /* 0 (default): tile of the inner kernels chosen by the autotuner
+                                (timed at engine creation and cached per arch, lattice, Ns,
+                                precision, links and nrhs; DWF_TUNE_CACHE names a file that
+                                keeps the cache across processes); k >= 1: candidate k
+                                (testing and reproducibility; DWF_EINVAL past the last)   */
 } dwf_solve_params;
 
 #define DWF_SYSTEM_D 0
@@ -145,6 +150,11 @@ typedef struct dwf_solve_stats {
     int reliable_updates;    /* restarts taken in reliable-update mode (p kept)           */
     int fallback;            /* 1 if the solve switched to defect correction              */
     int rhs_per_block;       /* right-hand sides per stencil workgroup, tuned per batch   */
+    int tile;                /* tile candidate of the inner kernels (1-based, as params.tile) */
+    int sites_per_block;     /* its 4D sites per workgroup                                */
+    int block_order;         /* its workgroup order: 0 lexicographic blocks, 1 t-fastest in
+                                XCD chunks of t-slices, w >= 2 the same with z-plane tiles
+                                of w blocks                                               */
     double true_residual;    /* ||b - D x|| / ||b||, FP64 full operator on the GPU        */
     double schur_residual;   /* ||b'' - C y|| / ||b''|| of the final iterate              */
     double seconds;          /* wall time of the solve on the device stream               */

@@ -50,12 +50,13 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_prec", ctypes.c_int), ("reliable", ctypes.c_int),
                 ("eps_inner", ctypes.c_double), ("maxiter", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("link_compress", ctypes.c_int), ("use_guess", ctypes.c_int),
-                ("debug_stall_after", ctypes.c_int), ("system", ctypes.c_int)]
+                ("debug_stall_after", ctypes.c_int), ("system", ctypes.c_int), ("tile", ctypes.c_int)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("reliable_updates", ctypes.c_int), ("fallback", ctypes.c_int), ("rhs_per_block", ctypes.c_int),
+                ("tile", ctypes.c_int), ("sites_per_block", ctypes.c_int), ("block_order", ctypes.c_int),
                 ("true_residual", ctypes.c_double), ("schur_residual", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("gflops", ctypes.c_double), ("hbm_gbytes", ctypes.c_double)]
 

@@ -119,6 +119,16 @@ int Workspace::alloc_state(int n, hipStream_t s) {
 using namespace dwf;
 
 dwf::Geom dwf_ctx::geom(int out_parity, bool fp64) const {
+    return geom_tile(out_parity, fp64 ? G64 : G32, dwf::ORDER_AUTO);
+}
+
+// Workgroup geometry: G 4D sites per workgroup, walked in block order `order`
+// (ORDER_AUTO: t-fastest, with z-plane tiles where a block's +-z neighbour
+// would otherwise be read more than 64 workgroups back; ORDER_PLAIN:
+// lexicographic blocks; ORDER_TFAST: t-fastest in XCD chunks of t-slices;
+// w >= 2: t-fastest with z-plane tiles of w blocks).  Orders that need blocks
+// to tile the t-slices or z-planes fall back to the plain order.
+dwf::Geom dwf_ctx::geom_tile(int out_parity, int G, int order) const {
     Geom g;
     g.Lx = dims[0];
     g.Ly = dims[1];
@@ -126,7 +136,7 @@ dwf::Geom dwf_ctx::geom(int out_parity, bool fp64) const {
     g.Lt = dims[3];
     g.Lxh = dims[0] / 2;
     g.Ns = Ns;
-    g.G = fp64 ? G64 : G32;
+    g.G = G;
     g.V4h = (int)V4h;
     g.out_parity = out_parity;
     g.antiper = opts.antiperiodic_t ? 1 : 0;
@@ -138,22 +148,27 @@ dwf::Geom dwf_ctx::geom(int out_parity, bool fp64) const {
     g.tchunk = 0;
     g.nsb0 = 0;
     g.tilew = 0;
-    if (g.xcd && V3h % g.G == 0) {
+    if (order != dwf::ORDER_PLAIN && g.xcd && V3h % g.G == 0) {
         g.nsb = (int)(V3h / g.G);
         g.tchunk = dims[3] % 8 == 0 ? dims[3] / 8 : dims[3];
-        // Tile the z-planes when the t-fastest order would put a block's +-z
-        // neighbour more than 64 workgroups back (an XCD holds about 128 at
-        // once): 24^3 planes (18 blocks, 6 t-slices per chunk) gain 2-8% per
-        // hop kernel, 16^3 planes (8 blocks, 4 t-slices) lose with tiles.
         const long plane = (long)g.Lxh * g.Ly;
         if (plane % g.G == 0) {
             g.nsb0 = (int)(plane / g.G);
-            if ((long)g.nsb0 * g.tchunk > 64)
-                for (int w = 6; w >= 2; --w)
-                    if (g.nsb0 % w == 0) {
-                        g.tilew = w;
-                        break;
-                    }
+            if (order == dwf::ORDER_AUTO) {
+                // Tile the z-planes when the t-fastest order would put a
+                // block's +-z neighbour more than 64 workgroups back (an XCD
+                // holds about 128 at once): 24^3 planes (18 blocks, 6 t-slices
+                // per chunk) gain 2-8% per hop kernel, 16^3 planes (8 blocks, 4
+                // t-slices) lose with tiles.
+                if ((long)g.nsb0 * g.tchunk > 64)
+                    for (int w = 6; w >= 2; --w)
+                        if (g.nsb0 % w == 0) {
+                            g.tilew = w;
+                            break;
+                        }
+            } else if (order >= 2 && g.nsb0 % order == 0) {
+                g.tilew = order;
+            }
         }
     }
     return g;
@@ -249,6 +264,7 @@ int check_params(const dwf_ctx* c, const dwf_solve_params& p) {
     if (p.maxiter < 1) return fail(DWF_EINVAL, "maxiter must be >= 1");
     if (p.link_compress < -1 || p.link_compress > 1) return fail(DWF_EINVAL, "link_compress must be -1, 0 or 1");
     if (p.system != DWF_SYSTEM_D && p.system != DWF_SYSTEM_CCDAG) return fail(DWF_EINVAL, "unknown system");
+    if (p.tile < 0) return fail(DWF_EINVAL, "tile must be >= 0");
     if (!c->su3 && p.inner_prec == DWF_PREC_FP32 && p.link_compress == 1)
         return fail(DWF_EINVAL, "12-real links need an SU(3) field (row 2 = conj(row 0 x row 1)); this field "
                                 "deviates by " + std::to_string(c->su3_dev));

@@ -57,6 +57,10 @@ struct DevBuf {
     T* as() const { return (T*)p; }
 };
 
+// Block orders of the stencil workgroups (dwf_ctx::geom_tile); w >= 2 means
+// t-fastest with z-plane tiles of w blocks.
+enum BlockOrder { ORDER_AUTO = -1, ORDER_PLAIN = 0, ORDER_TFAST = 1 };
+
 // Link formats held per parity.
 enum LinkFmt { LINK_D18 = 0, LINK_S18 = 1, LINK_S12 = 2, LINK_H12 = 3, LINK_NFMT = 4 };
 
@@ -142,6 +146,9 @@ class EngineBase {
     virtual ~EngineBase() {}
     virtual int capacity() const = 0;
     virtual int rhs_per_block() const = 0;  // tuned right-hand sides per stencil workgroup
+    // the tuned tile of the inner kernels: candidate index (0-based), 4D sites
+    // per workgroup, block order (BlockOrder or tile width)
+    virtual void tile(int* index, int* sites, int* order) const = 0;
     virtual int phase(int slot) const = 0;
     virtual int busy() const = 0;  // slots not free
     virtual int pending() const = 0;  // slots neither free nor done
@@ -163,6 +170,12 @@ class EngineBase {
 };
 
 int make_engine(dwf_ctx* c, const dwf_solve_params& p, int K, hipStream_t s, std::unique_ptr<EngineBase>* out);
+// a tile of the inner kernels: G sites per workgroup, requested block order,
+// the order its geometry walks (BlockOrder or tile width)
+struct TileCand {
+    int G, order, eff;
+};
+std::vector<TileCand> tile_candidates(const dwf_ctx* c, bool fp64);
 // link format of an inner solve: the params' choice, with auto resolved by the
 // field's SU(3) check (12-real only for SU(3) fields)
 int link_format(const dwf_ctx* c, const dwf_solve_params& p);
@@ -203,6 +216,7 @@ struct dwf_ctx {
     dwf::DevBuf prop_ws;   // propagator: wall source, 5D source and 5D solution per source
 
     dwf::Geom geom(int out_parity, bool fp64) const;
+    dwf::Geom geom_tile(int out_parity, int G, int order) const;
     const dwf::TableSet* table_set(double mq_val, int* rc);
     int ensure_partials(size_t nblocks_times_nrhs);
     long spinor_elems() const { return V4 * Ns * 24; }

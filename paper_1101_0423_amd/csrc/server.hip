@@ -350,6 +350,9 @@ void lane_main(Lane* L) {
             o.seconds = res.seconds;
             o.gflops = res.seconds > 0 ? res.flops / res.seconds * 1e-9 : 0;
             o.hbm_gbytes = res.bytes * 1e-9;
+            o.rhs_per_block = eng->rhs_per_block();
+            eng->tile(&o.tile, &o.sites_per_block, &o.block_order);
+            o.tile += 1;
             std::lock_guard<std::mutex> lk(S.mu);
             L->slot[r] = nullptr;
             S.lat.push_back(std::chrono::duration<double>(Clock::now() - q->t_submit).count());

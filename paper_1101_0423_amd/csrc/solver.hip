@@ -58,6 +58,105 @@ double bytes_per_iter(const dwf_ctx* c, int inner_prec, int link_fmt) {
     return (double)c->V5h * (15.0 * sb + 2.0 * yb) + 4.0 * (double)c->V4h * 8.0 * link_bytes(link_fmt);
 }
 
+// ---------------------------------------------------------------------------
+// Tile candidates of the inner kernels and the tuning cache
+// ---------------------------------------------------------------------------
+
+// The inner kernels' tiles the autotuner tries: the default sites per
+// workgroup and half of it (while a workgroup keeps at least one wave), each
+// in the automatic block order, then plain, t-fastest and tiled orders
+// (geometries equal to an earlier candidate are left out).  A fixed
+// dwf_opts.sites_per_block keeps its G.  Candidate 0 is the automatic order
+// at the default G.
+std::vector<TileCand> tile_candidates(const dwf_ctx* c, bool fp64) {
+    const int G0 = fp64 ? c->G64 : c->G32;
+    std::vector<int> Gs{G0};
+    if (c->opts.sites_per_block <= 0 && G0 % 2 == 0 && (G0 / 2) * c->Ns >= 64) Gs.push_back(G0 / 2);
+    std::vector<TileCand> out;
+    std::vector<Geom> seen;
+    auto same = [](const Geom& a, const Geom& b) {
+        return a.G == b.G && a.nsb == b.nsb && a.tchunk == b.tchunk && a.nsb0 == b.nsb0 && a.tilew == b.tilew;
+    };
+    for (int G : Gs)
+        for (int order : {(int)ORDER_AUTO, (int)ORDER_TFAST, (int)ORDER_PLAIN, 2, 3, 4, 6}) {
+            const Geom g = c->geom_tile(0, G, order);
+            if (order >= 2 && g.tilew != order) continue;  // not a whole number of tiles per plane
+            bool dup = false;
+            for (auto& h : seen) dup |= same(g, h);
+            if (dup) continue;
+            seen.push_back(g);
+            // report the order the geometry actually walks
+            const int eff = g.nsb == 0 ? ORDER_PLAIN : g.tilew >= 2 ? g.tilew : ORDER_TFAST;
+            out.push_back(TileCand{G, order, eff});
+        }
+    return out;
+}
+
+namespace {
+
+struct TuneVal {
+    int tile, kgroup;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneVal> g_tune;
+bool g_tune_loaded = false;
+
+// The tuning cache: in the process, and in the file named by DWF_TUNE_CACHE
+// (lines "key tile kgroup"), read once and appended to, when it is set.
+void tune_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("DWF_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char key[512];
+    int t, k;
+    while (fscanf(f, "%511s %d %d", key, &t, &k) == 3) g_tune[key] = TuneVal{t, k};
+    fclose(f);
+}
+
+bool tune_get(const std::string& key, TuneVal* v) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *v = it->second;
+    return true;
+}
+
+void tune_put(const std::string& key, TuneVal v) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load();
+    g_tune[key] = v;
+    if (const char* path = getenv("DWF_TUNE_CACHE")) {
+        if (FILE* f = fopen(path, "a")) {
+            fprintf(f, "%s %d %d\n", key.c_str(), v.tile, v.kgroup);
+            fclose(f);
+        }
+    }
+}
+
+std::string arch_name(int device) {
+    static std::mutex mu;
+    static std::map<int, std::string> names;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = names.find(device);
+    if (it != names.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string n = "unknown";
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        n = prop.gcnArchName;
+        for (auto& ch : n)
+            if (ch == ' ' || ch == ':') ch = '_';
+    }
+    names[device] = n;
+    return n;
+}
+
+}  // namespace
+
 namespace {
 
 // half fields of an engine
@@ -93,8 +192,8 @@ struct SlotCtl {
 template <class Real, class F, class FY, class LF>
 class Engine : public EngineBase {
   public:
-    Engine(dwf_ctx* c_, int prec_, int fmt_, int K_, hipStream_t s_, LF e, LF o)
-        : c(c_), prec(prec_), link_fmt(fmt_), K(K_), s(s_), lk{e, o},
+    Engine(dwf_ctx* c_, int prec_, int fmt_, int K_, hipStream_t s_, LF e, LF o, int forced_tile_)
+        : c(c_), prec(prec_), link_fmt(fmt_), K(K_), s(s_), lk{e, o}, forced_tile(forced_tile_),
           lk64{LinkD18{c_->links[0][LINK_D18].as<double>()}, LinkD18{c_->links[1][LINK_D18].as<double>()}},
           sl((size_t)K_) {}
     ~Engine() override {
@@ -123,7 +222,12 @@ class Engine : public EngineBase {
         TS = (long)tables_size(c->Ns);
         if ((rc = tabs64.alloc((size_t)TS * K * sizeof(double))) || (rc = tabs32.alloc((size_t)TS * K * sizeof(float))))
             return rc;
-        nbmax = std::max(c->geom(0, true).nblocks, c->geom(0, false).nblocks);
+        cands = tile_candidates(c, sizeof(Real) == 8);
+        if (forced_tile >= (int)cands.size())
+            return fail(DWF_EINVAL, "params.tile: there are " + std::to_string(cands.size()) + " tile candidates");
+        nbmax = c->geom(0, true).nblocks;
+        for (auto& t : cands) nbmax = std::max(nbmax, c->geom_tile(0, t.G, t.order).nblocks);
+        set_tile(forced_tile >= 0 ? forced_tile : 0);
         if ((rc = aux.alloc((size_t)nbmax * K * sizeof(double) + ((size_t)NMASK * K + NLIST * (K + 1)) * sizeof(int))))
             return rc;
         for (int m = 0; m < NMASK; ++m) dmask[m] = (int*)(aux.as<double>() + (size_t)nbmax * K) + (size_t)m * K;
@@ -142,6 +246,11 @@ class Engine : public EngineBase {
 
     int capacity() const override { return K; }
     int rhs_per_block() const override { return kgroup; }
+    void tile(int* index, int* sites, int* order) const override {
+        *index = tidx;
+        *sites = cands[tidx].G;
+        *order = cands[tidx].eff;
+    }
     int phase(int r) const override { return sl[r].phase; }
     int busy() const override {
         int n = 0;
@@ -247,23 +356,32 @@ class Engine : public EngineBase {
 
     int time_kernels(int launches, double* ms, double* bytes) override;
 
-    // Right-hand sides per workgroup: reading each link once for more of them
-    // saves link bytes, while fewer keep the neighbour re-reads of adjacent
-    // workgroups in L2.  Time one inner iteration (every slot forced on) for
-    // each candidate and keep the fastest.  Runs before any graph capture; the
-    // fields may hold anything, which the solve overwrites before use.
+    // The tile of the inner kernels (sites per workgroup and block order) and
+    // the right-hand sides per workgroup: each candidate is timed over one
+    // inner iteration (every slot forced on; the fields may hold anything,
+    // which the solve overwrites before use), tiles first with one right-hand
+    // side per workgroup, then the group size with the chosen tile.  Reading
+    // each link once for more right-hand sides saves link bytes, while fewer
+    // keep the neighbour re-reads of adjacent workgroups in L2.  Results are
+    // cached per (arch, lattice, Ns, precision, links, K, fixed G).  Runs
+    // before any graph is built.
     int autotune() {
-        kgroup = K;
-        if (K == 1) return DWF_OK;
-        std::vector<int> cand;
-        for (int k : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32})
-            if (k < K) cand.push_back(k);
-        cand.push_back(K);
+        const std::string key = arch_name(c->device) + ":" + std::to_string(c->dims[0]) + "x" +
+                                std::to_string(c->dims[1]) + "x" + std::to_string(c->dims[2]) + "x" +
+                                std::to_string(c->dims[3]) + ":ns" + std::to_string(c->Ns) + ":p" +
+                                std::to_string(prec) + ":l" + std::to_string(link_fmt) + ":k" + std::to_string(K) +
+                                ":g" + std::to_string(c->opts.sites_per_block) + ":x" +
+                                std::to_string(c->opts.xcd_remap < 0 ? 0 : 1);
+        TuneVal v;
+        if (forced_tile < 0 && tune_get(key, &v) && v.tile >= 0 && v.tile < (int)cands.size() && v.kgroup >= 1 &&
+            v.kgroup <= K) {
+            set_tile(v.tile);
+            kgroup = v.kgroup;
+            return DWF_OK;
+        }
         hipEvent_t e0, e1;
         DWF_HIP(hipEventCreate(&e0));
         DWF_HIP(hipEventCreate(&e1));
-        double best = 1e30;
-        int bestk = K;
         hipError_t e = hipSuccess;
         auto pass = [&]() {
             hipError_t r = kE(nullptr);
@@ -273,26 +391,57 @@ class Engine : public EngineBase {
             if (r == hipSuccess) r = kD(nullptr);
             return r;
         };
-        for (int k : cand) {
-            kgroup = k;
+        auto timed = [&](float* ms) {
             e = pass();
             if (e == hipSuccess) e = hipEventRecord(e0, s);
             for (int i = 0; i < 2 && e == hipSuccess; ++i) e = pass();
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) break;
-            if (getenv("DWF_VERBOSE")) fprintf(stderr, "[dwf] autotune K=%d: %d per workgroup %.3f ms\n", K, k, ms / 2);
-            if (ms < best) {
-                best = ms;
-                bestk = k;
+            if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+            return e == hipSuccess;
+        };
+        if (forced_tile < 0 && cands.size() > 1) {
+            kgroup = 1;
+            float best = 1e30f;
+            int besti = 0;
+            for (int i = 0; i < (int)cands.size(); ++i) {
+                set_tile(i);
+                float ms = 0;
+                if (!timed(&ms)) break;
+                if (verbose)
+                    fprintf(stderr, "[dwf] autotune K=%d: tile %d (G=%d order=%d) %.3f ms\n", K, i, cands[i].G,
+                            cands[i].eff, ms / 2);
+                if (ms < best) {
+                    best = ms;
+                    besti = i;
+                }
             }
+            set_tile(besti);
+        }
+        kgroup = K;
+        if (K > 1 && e == hipSuccess) {
+            std::vector<int> cand;
+            for (int k : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32})
+                if (k < K) cand.push_back(k);
+            cand.push_back(K);
+            float best = 1e30f;
+            int bestk = K;
+            for (int k : cand) {
+                kgroup = k;
+                float ms = 0;
+                if (!timed(&ms)) break;
+                if (verbose) fprintf(stderr, "[dwf] autotune K=%d: %d per workgroup %.3f ms\n", K, k, ms / 2);
+                if (ms < best) {
+                    best = ms;
+                    bestk = k;
+                }
+            }
+            kgroup = bestk;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (e != hipSuccess) return fail(DWF_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
-        kgroup = bestk;
+        if (forced_tile < 0) tune_put(key, TuneVal{tidx, kgroup});
         return DWF_OK;
     }
 
@@ -301,6 +450,14 @@ class Engine : public EngineBase {
     int prec, link_fmt, K;
     hipStream_t s;
     LF lk[2];
+    int forced_tile;               // >= 0: params.tile - 1 (no tuning of the tile)
+    std::vector<TileCand> cands;   // tiles of the inner kernels
+    int tidx = 0;                  // the tile in use
+    Geom gt[2];                    // its geometry per output parity
+    void set_tile(int i) {
+        tidx = i;
+        for (int par = 0; par < 2; ++par) gt[par] = c->geom_tile(par, cands[i].G, cands[i].order);
+    }
     LinkD18 lk64[2];
     std::vector<SlotCtl> sl;
     Workspace w;
@@ -388,7 +545,7 @@ class Engine : public EngineBase {
 
     // ---------------- kernels ----------------
     Geom g64(int par) const { return c->geom(par, true); }
-    Geom glo(int par) const { return c->geom(par, sizeof(Real) == 8); }
+    Geom glo(int par) const { return gt[par]; }
     FD d(int i) { return w.f(i).fd(); }
     F lo(int i) { return fld<F>(w.f(i)); }
     FY ylo() { return fld<FY>(w.f(L_Y)); }
@@ -969,8 +1126,9 @@ int Engine<Real, F, FY, LF>::time_kernels(int launches, double* ms, double* byte
 }
 
 template <class Real, class F, class FY, class LF>
-int build(dwf_ctx* c, int prec, int fmt, int K, hipStream_t s, LF e, LF o, std::unique_ptr<EngineBase>* out) {
-    std::unique_ptr<Engine<Real, F, FY, LF>> eng(new Engine<Real, F, FY, LF>(c, prec, fmt, K, s, e, o));
+int build(dwf_ctx* c, int prec, int fmt, int K, hipStream_t s, LF e, LF o, int tile,
+          std::unique_ptr<EngineBase>* out) {
+    std::unique_ptr<Engine<Real, F, FY, LF>> eng(new Engine<Real, F, FY, LF>(c, prec, fmt, K, s, e, o, tile - 1));
     int rc = eng->init();
     if (rc) return rc;
     *out = std::move(eng);
@@ -978,7 +1136,8 @@ int build(dwf_ctx* c, int prec, int fmt, int K, hipStream_t s, LF e, LF o, std::
 }
 
 std::string engine_key(const dwf_ctx* c, const dwf_solve_params& p, int nrhs) {
-    return "solve:" + std::to_string(p.inner_prec) + ":" + std::to_string(link_format(c, p)) + ":" +
+    return "solve:" + std::to_string(p.inner_prec) + ":" + std::to_string(link_format(c, p)) + ":t" +
+           std::to_string(p.tile) + ":" +
            std::to_string(nrhs);
 }
 
@@ -989,19 +1148,19 @@ int make_engine(dwf_ctx* c, const dwf_solve_params& p, int K, hipStream_t s, std
         case DWF_PREC_FP64:
             return build<double, FD, FD, LinkD18>(c, DWF_PREC_FP64, LINK_D18, K, s,
                                                   LinkD18{c->links[0][LINK_D18].as<double>()},
-                                                  LinkD18{c->links[1][LINK_D18].as<double>()}, out);
+                                                  LinkD18{c->links[1][LINK_D18].as<double>()}, p.tile, out);
         case DWF_PREC_FP32:
             if (link_format(c, p) == LINK_S12)
                 return build<float, FS, FS, LinkS12>(c, DWF_PREC_FP32, LINK_S12, K, s,
                                                      LinkS12{c->links[0][LINK_S12].as<float>()},
-                                                     LinkS12{c->links[1][LINK_S12].as<float>()}, out);
+                                                     LinkS12{c->links[1][LINK_S12].as<float>()}, p.tile, out);
             return build<float, FS, FS, LinkS18>(c, DWF_PREC_FP32, LINK_S18, K, s,
                                                  LinkS18{c->links[0][LINK_S18].as<float>()},
-                                                 LinkS18{c->links[1][LINK_S18].as<float>()}, out);
+                                                 LinkS18{c->links[1][LINK_S18].as<float>()}, p.tile, out);
         default:
             return build<float, FH, FS, LinkH12>(c, DWF_PREC_FP16, LINK_H12, K, s,
                                                  LinkH12{c->links[0][LINK_H12].as<_Float16>()},
-                                                 LinkH12{c->links[1][LINK_H12].as<_Float16>()}, out);
+                                                 LinkH12{c->links[1][LINK_H12].as<_Float16>()}, p.tile, out);
     }
 }
 
@@ -1011,7 +1170,9 @@ size_t engine_bytes(const dwf_ctx* c, int prec, int K) {
     const long f64 = field_elems(c->V5h, DWF_PREC_FP64);
     size_t per = ((size_t)NF64 * f64 + 5 * (size_t)lo + (size_t)y) * 16;
     if (prec == DWF_PREC_FP16) per += 5 * (size_t)(((c->V5h + 1023) / 1024) * 1024) * sizeof(float);
-    const size_t nb = (size_t)std::max(c->geom(0, true).nblocks, c->geom(0, false).nblocks);
+    size_t nb = (size_t)c->geom(0, true).nblocks;
+    for (auto& t : tile_candidates(c, prec == DWF_PREC_FP64))
+        nb = std::max(nb, (size_t)c->geom_tile(0, t.G, t.order).nblocks);
     per += tables_size(c->Ns) * 12 + nb * sizeof(double) + 96;
     return per * (size_t)K;
 }
@@ -1097,6 +1258,8 @@ int solve(dwf_ctx* c, const double* b_dev, double* x_dev, int nrhs, const dwf_so
             o.reliable_updates = res[r].reliable_updates;
             o.fallback = res[r].fallback;
             o.rhs_per_block = eng->rhs_per_block();
+            eng->tile(&o.tile, &o.sites_per_block, &o.block_order);
+            o.tile += 1;
             o.true_residual = res[r].true_residual;
             o.schur_residual = res[r].schur_residual;
             // the batch shares the device: time, rate and bytes are the batch's

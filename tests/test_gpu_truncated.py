@@ -79,3 +79,49 @@ def test_truncated_solve_matches_oracle_iterates(name, prec):
         print(f"[trunc]   k={k}: element-wise {e_el:.3e}, norm-wise {e_n:.3e}", flush=True)
         assert e_el <= BAR[ip], (k, e_el)
         assert e_n <= BAR[ip], (k, e_n)
+
+
+# 24 x 24 z-planes: 18 (FP32) or 36 (half-size workgroups) blocks per plane,
+# so the tiled orders of widths 2, 3, 4 and 6 are all candidates
+_rt = np.random.default_rng(95)
+TILED = lambda: Problem((24, 24, 2, 32), 16, 1.8, 0.02, *(2 * [_rt.uniform(0.5, 1.5, 16)]), 0.5, 63, 64)
+
+
+@pytest.mark.parametrize("name", ["odwf16", "tiled24"])
+def test_every_tile_candidate_matches_oracle_iterates(name):
+    """Every tile the autotuner may choose (sites per workgroup x block order),
+    forced through params.tile, runs the same iterates as the oracle: 2
+    iterations of FP32 CG with 12-real links, element-wise to the FP32 bar.
+    The autotuned solve reports one of them."""
+    import paper_1101_0423_amd as dwf
+    if name == "odwf16":
+        P, c, ref = problem("odwf16")
+        exp = ref[2]
+        own = False
+    else:
+        P = TILED()
+        exp, info = oracle.solve(*P.oargs(), P.b, tol=1e-300, maxiter=2, bct=P.bct)
+        assert info["schur_res"] < 1.0
+        c = P.context()
+        own = True
+    try:
+        seen = set()
+        for t in range(1, 40):
+            try:
+                x, st, rc = c.solve(P.b, inner_prec=1, link_compress=1, reliable=0, maxiter=2, tile=t)
+            except dwf.DwfError as e:
+                assert e.code == dwf.DWF_EINVAL and "tile" in str(e)
+                break
+            s = st[0]
+            seen.add((s["sites_per_block"], s["block_order"]))
+            e_el = max_rel(x, exp)
+            print(f"[tile] {name} candidate {t}: G={s['sites_per_block']} order={s['block_order']} "
+                  f"element-wise {e_el:.3e}", flush=True)
+            assert s["tile"] == t and e_el <= BAR[1], (t, e_el)
+        assert len(seen) >= 3, seen
+        x, st, rc = c.solve(P.b, inner_prec=1, link_compress=1, reliable=0, maxiter=2)
+        assert (st[0]["sites_per_block"], st[0]["block_order"]) in seen and st[0]["tile"] >= 1
+        assert max_rel(x, exp) <= BAR[1]
+    finally:
+        if own:
+            c.close()
