@@ -114,7 +114,10 @@ def cpu_baseline(w, U, b, n1=2, n2=12, reps=3):
                 seconds_per_iteration=per_it)
 
 
-KERNEL_KEYS = [("ProCgE", "cg_dir_m5t"), ("EpiCgD", "hop_oe_m5_cgupd"), ("EpiCgB", "hop_oe_g5_sub"),
+# the inner kernels of dwf_time_kernels (T once per cycle, then one iteration A B C D)
+KERNEL_NAMES = {"T": "cycle_start_m5t", "A": "hop_eo_m5t", "B": "hop_oe_g5_dir", "C": "hop_eo_m5",
+                "D": "hop_oe_m5_cgupd_m5t"}
+KERNEL_KEYS = [("EpiCgD", "hop_oe_m5_cgupd_m5t"), ("EpiCgB", "hop_oe_g5_dir"),
                ("k_finish", "finish_reduction"), ("EpiOuter", "outer_residual_fp64"),
                ("k_stream_copy<true>", "copy_nontemporal_1GiB"), ("k_stream_copy<false>", "copy_cached_1GiB")]
 
@@ -125,13 +128,16 @@ def kernel_label(name):
             return label
     if "k_dwf<" in name:
         # k_dwf<Real, F, LF, NSMAX, HOP, MIXM, REGMIX, Pro, Epi>: the low-precision
-        # hop-only kernels A (M5^T, mode 3) and C (M5, mode 2) store their result
+        # kernels A (hop, M5^T: mode 3), C (hop, M5: mode 2) and T (no hop, M5^T
+        # gamma_5: mode 3) store their result
         args = [a.strip() for a in name.split("k_dwf<", 1)[1].split(",")]
-        if len(args) >= 9 and args[0] == "float" and args[4] == "true" and "EpiStore" in name:
-            if args[5] == "3":
+        if len(args) >= 9 and args[0] == "float" and "EpiStore" in name:
+            if args[4] == "true" and args[5] == "3":
                 return "hop_eo_m5t"
-            if args[5] == "2":
+            if args[4] == "true" and args[5] == "2":
                 return "hop_eo_m5"
+            if args[4] == "false" and args[5] == "3":
+                return "cycle_start_m5t"
     return name[:90]
 
 
@@ -214,7 +220,7 @@ def run_batch(nrhs=12, log=True):
     ms_1, by_1 = ctx.time_kernels(params=params, nrhs=1, launches=5)
     flops = sum(s["gflops"] for s in st_b[:1]) * st_b[0]["seconds"] * 1e9
     gbytes = st_b[0]["hbm_gbytes"]
-    names = {"E": "cg_dir_m5t", "A": "hop_eo_m5t", "B": "hop_oe_g5_sub", "C": "hop_eo_m5", "D": "hop_oe_m5_cgupd"}
+    names = KERNEL_NAMES
     kern = {names[k]: dict(ms_batch=round(ms_b[k], 4), ms_single=round(ms_1[k], 4),
                            gbs_batch=round(by_b[k] / (ms_b[k] * 1e-3) * 1e-9, 1),
                            gbs_single=round(by_1[k] / (ms_1[k] * 1e-3) * 1e-9, 1)) for k in ms_b}
@@ -448,8 +454,8 @@ def main():
         summarize_rocpd(args.summarize_rocpd)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; there is no multi-GPU path "
-              "(a single solve would shard by 4D domain decomposition, see DESIGN.md)", file=sys.stderr)
+        print("bench.py: measures one GPU only; there is no multi-GPU path "
+              "(a single solve would shard by 4D domain decomposition of the lattice)", file=sys.stderr)
         sys.exit(2)
 
     if args.mode == "batch":
@@ -563,7 +569,7 @@ def run_solve(dwf, ctx, bd, xd, prec, lc, steps, warmup, launches, say):
     gbytes = sum(s["hbm_gbytes"] for s, _ in stats)
     ms, by = ctx.time_kernels(params=params, launches=launches)
     dom = max(ms, key=ms.get)
-    names = {"E": "cg_dir_m5t", "A": "hop_eo_m5t", "B": "hop_oe_g5_sub", "C": "hop_eo_m5", "D": "hop_oe_m5_cgupd"}
+    names = KERNEL_NAMES
     achieved = by[dom] / (ms[dom] * 1e-3) * 1e-9
     return dict(gflops=round(flops / elapsed * 1e-9, 2), hbm_gbs=round(gbytes / elapsed, 1),
                 ms_per_step=round(elapsed / steps * 1e3, 3), iters=stats[-1][0]["iters"],

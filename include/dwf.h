@@ -158,7 +158,9 @@ typedef struct dwf_solve_stats {
     double true_residual;    /* ||b - D x|| / ||b||, FP64 full operator on the GPU        */
     double schur_residual;   /* ||b'' - C y|| / ||b''|| of the final iterate              */
     double seconds;          /* wall time of the solve on the device stream               */
-    double gflops;           /* paper-convention flops / seconds (see DESIGN)             */
+    double gflops;           /* flops of the method / seconds: per inner iteration and odd
+                                5D site 5280 + 192 Ns + 288 (four hops, four fifth-
+                                dimension matrices, the CG vector algebra)              */
     double hbm_gbytes;       /* algorithmic HBM bytes moved / 1e9                         */
 } dwf_solve_stats;
 
@@ -333,10 +335,15 @@ int dwf_server_stats_get(dwf_server_stats *out, int reset);
 
 /*
  * dwf_time_kernels -- profiling aid: average device time (milliseconds) of
- * each kernel of one inner CG iteration, in the order E, A, B, C, D (see
- * DESIGN), over `launches` back-to-back launches on the context's stream
- * bracketed by HIP events, and the algorithmic HBM bytes one launch must move
- * (every operand read or written once).  Uses the workspace left by the last
+ * the inner CG kernels over `launches` back-to-back launches on the context's
+ * stream bracketed by HIP events, and the algorithmic HBM bytes one launch
+ * must move (every operand read or written once).  Entries, in launch order:
+ *   0  T: t1 = M5^T gamma_5 r, once at the start of an inner cycle;
+ *   1  A: t2 = M5^T D^EO t1;
+ *   2  B: u = r - gamma_5 D^OE t2 + beta u (the direction as C^dag p), |u|^2;
+ *   3  C: t3 = M5 D^EO u;
+ *   4  D: r -= alpha (u - M5 D^OE t3), y += alpha u, |r|^2, t1 = M5^T gamma_5 r.
+ * One inner iteration is A, B, C, D (Algorithm 1, Secs. 3.2-3.5).  Uses the workspace left by the last
  * dwf_solve/dwf_solve_dev with the same params and nrhs (DWF_EINVAL if there
  * is none); it overwrites that workspace's low-precision vectors.
  */

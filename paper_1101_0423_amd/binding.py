@@ -365,12 +365,13 @@ class Context:
         return [x.as_dict() for x in st], rc
 
     def time_kernels(self, params=None, nrhs=1, launches=20, **kw):
-        """Average ms and algorithmic bytes of the inner kernels E, A, B, C, D."""
+        """Average ms and algorithmic bytes of the inner kernels: T (the
+        cycle-start t1 = M5^T g5 r) and the iteration's A, B, C, D."""
         p = params if params is not None else default_params(**kw)
         ms = np.zeros(5)
         by = np.zeros(5)
         _check(lib().dwf_time_kernels(self._h, ctypes.byref(p), nrhs, launches, _ptr(ms), _ptr(by)))
-        return dict(zip("EABCD", ms)), dict(zip("EABCD", by))
+        return dict(zip("TABCD", ms)), dict(zip("TABCD", by))
 
     # -- serving ---------------------------------------------------------
     def submit(self, b, mq=None, params=None, **kw):

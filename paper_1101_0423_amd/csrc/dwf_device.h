@@ -36,11 +36,25 @@ namespace dwf {
 // slices of one block are adjacent (one wave reads whole 256-byte runs) and
 // all of a 4D site's data is one contiguous chunk.
 
+// Every field type has Ptrs, the pointers of one field, and with(q), a field of
+// the same layout (Ns, right-hand-side strides) at q: a kernel that touches
+// several fields of one layout passes one full field and the others' Ptrs,
+// which keeps its arguments within the scalar registers.
+
 struct FD {  // FP64 storage and arithmetic
     using real = double;
     double2* p;
     long ns;       // Ns (elements between component blocks of a site)
     long rstride;  // elements between right-hand sides
+    struct Ptrs {
+        double2* p;
+    };
+    __host__ __device__ Ptrs ptrs() const { return Ptrs{p}; }
+    __host__ __device__ FD with(Ptrs q) const {
+        FD f = *this;
+        f.p = q.p;
+        return f;
+    }
     __device__ __forceinline__ const double2* at(int rhs, long i, int s) const {
         return p + rhs * rstride + 12 * i - 11 * (long)s;
     }
@@ -98,6 +112,15 @@ struct FS {  // FP32 storage
     float4* p;
     long ns;
     long rstride;
+    struct Ptrs {
+        float4* p;
+    };
+    __host__ __device__ Ptrs ptrs() const { return Ptrs{p}; }
+    __host__ __device__ FS with(Ptrs q) const {
+        FS f = *this;
+        f.p = q.p;
+        return f;
+    }
     __device__ __forceinline__ const float4* at(int rhs, long i, int s) const {
         return p + rhs * rstride + 6 * i - 5 * (long)s;
     }
@@ -169,6 +192,17 @@ struct FH {  // binary16 storage with one FP32 scale per 5D site; FP32 arithmeti
     long ns;
     long rstride;   // data elements between right-hand sides
     long nrstride;  // norm elements between right-hand sides
+    struct Ptrs {
+        uint4* p;
+        float* nrm;
+    };
+    __host__ __device__ Ptrs ptrs() const { return Ptrs{p, nrm}; }
+    __host__ __device__ FH with(Ptrs q) const {
+        FH f = *this;
+        f.p = q.p;
+        f.nrm = q.nrm;
+        return f;
+    }
     __device__ __forceinline__ const uint4* at(int rhs, long i, int s) const {
         return p + rhs * rstride + 3 * i - 2 * (long)s;
     }
@@ -837,11 +871,78 @@ __device__ __forceinline__ void mix_reg16(Real* v, const Real* __restrict__ C, i
 //   phase 2: the fifth-dimension matrix per 4D site  [MIXM != MIX_NONE]
 //            (LDS transpose: lanes switch from (site, s) to (site, column))
 //   phase 3: epilogue(site, s, v) -> norm contribution, block-reduced
+//   phase 4: M5^T gamma_5 on the vector the epilogue left in v, stored by
+//            epi.post                                [epilogue with kPost]
 // One workgroup covers G consecutive 4D half sites x all Ns slices, lane
 // (sl, s) = (tid / Ns, tid % Ns), so the SoA loads of consecutive lanes are
 // consecutive 16-byte vectors and the G x 8 links are staged once in LDS
 // and shared by the Ns slices (and by every right-hand side).
 // ---------------------------------------------------------------------------
+
+// An epilogue with a second output: kPost = true, a member ptab (the offset
+// of the M5^T gamma_5 coefficients from the kernel's table, indexed per
+// right-hand side in the same way) and post(rhs, i, s, v), which stores
+// M5^T gamma_5 of what operator() left in v.
+template <class E, class = void>
+struct EpiPost {
+    static constexpr bool value = false;
+};
+template <class E>
+struct EpiPost<E, std::void_t<decltype(E::kPost)>> {
+    static constexpr bool value = E::kPost;
+};
+
+// The fifth-dimension matrix through LDS: each lane writes its (site, s)
+// vector, the workgroup mixes the columns (chirality, site, real component),
+// and each lane reads its vector back.  Every thread of the workgroup calls it.
+template <class Real, int NSMAX, int MODE>
+__device__ __forceinline__ void mix_lds(Real* v, Real* hb, const Real* __restrict__ tb, int Ns, int nsites, int sl,
+                                        int s, bool act, int hs, int tid, int T) {
+    if (act) {
+        Real* dst = hb + sl * hs + s * 24;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) dst[k] = v[k];
+    }
+    __syncthreads();
+    // columns (chirality ch, site, real component c of that chirality);
+    // every wave handles columns of one chirality so that the table
+    // entries are wave-uniform (scalar loads).
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int nwaves = (T + 63) >> 6;
+    const int ncol = nsites * 12;
+    const int nch = (ncol + 63) >> 6;
+    for (int c = wave; c < 2 * nch; c += nwaves) {
+        const int ch = c / nch;
+        const int col = (c - ch * nch) * 64 + lane;
+        if (col < ncol) {
+            const int cs = col / 12, cc = col - cs * 12;
+            Real* base = hb + cs * hs + ch * 12 + cc;
+            if constexpr (MODE == MIX_DENSE)
+                mix_dense<Real, NSMAX>(base, tb + ch * Ns * Ns, Ns);
+            else  // M5: reversed for L_-; M5^T: reversed for L_+^T = L_-
+                mix_structured<Real, NSMAX, MODE>(base, tb + ch * 6 * Ns, Ns, (ch == 1) != (MODE == MIX_AS));
+        }
+    }
+    __syncthreads();
+    if (act) {
+        const Real* src = hb + sl * hs + s * 24;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) v[k] = src[k];
+    }
+}
+
+// M5 (MIX_SA) or M5^T (MIX_AS) in registers at Ns = 16; every lane of the
+// workgroup calls it (rows of inactive sites are whole rows)
+template <class Real, int MODE>
+__device__ __forceinline__ void mix_reg(Real* v, const Real* __restrict__ tb, int s) {
+    // the coefficient loads stay after what precedes, whose register peak
+    // they would otherwise raise
+    __builtin_amdgcn_sched_barrier(0);
+    constexpr bool rev0 = MODE == MIX_AS, rev1 = MODE != MIX_AS;  // M5: L_- reversed; M5^T: L_+^T
+    mix_reg16<Real, MODE, rev0>(v, tb, s);
+    mix_reg16<Real, MODE, rev1>(v + 12, tb + 6 * 16, s);
+}
 
 struct KOpt {
     const int* live;       // per right-hand side; NULL = always run
@@ -891,6 +992,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::i
 k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, KOpt o) {
     // REGMIX: Ns == 16, M5 / M5^T applied in registers (no LDS transpose)
     constexpr bool MIX = MIXM != MIX_NONE && !REGMIX;
+    // phase 4 runs in the same way as phase 2 (registers or LDS)
+    constexpr bool POST = EpiPost<Epi>::value;
+    static_assert(!POST || MIXM == MIX_SA || MIXM == MIX_AS, "phase 4 needs a kernel with a structured phase 2");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int LS = LdsLink<Real>::STR;
     const int Ns = g.Ns;
@@ -967,54 +1071,21 @@ k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, 
 #pragma unroll
             for (int k = 0; k < 24; ++k) v[k] = 0;
         }
-        if constexpr (MIX) {
-            if (act) {
-                Real* dst = hb + sl * hs + s * 24;
-#pragma unroll
-                for (int k = 0; k < 24; ++k) dst[k] = v[k];
-            }
-            __syncthreads();
-            // columns (chirality ch, site, real component c of that chirality);
-            // every wave handles columns of one chirality so that the table
-            // entries are wave-uniform (scalar loads).
-            const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-            const int lane = tid & 63;
-            const int nwaves = (T + 63) >> 6;
-            const int ncol = nsites * 12;
-            const int nch = (ncol + 63) >> 6;
-            const Real* tb = table + rhs * o.table_rstride;
-            for (int c = wave; c < 2 * nch; c += nwaves) {
-                const int ch = c / nch;
-                const int col = (c - ch * nch) * 64 + lane;
-                if (col < ncol) {
-                    const int cs = col / 12, cc = col - cs * 12;
-                    Real* base = hb + cs * hs + ch * 12 + cc;
-                    if constexpr (MIXM == MIX_DENSE)
-                        mix_dense<Real, NSMAX>(base, tb + ch * Ns * Ns, Ns);
-                    else  // M5: reversed for L_-; M5^T: reversed for L_+^T = L_-
-                        mix_structured<Real, NSMAX, MIXM>(base, tb + ch * 6 * Ns, Ns,
-                                                          (ch == 1) != (MIXM == MIX_AS));
-                }
-            }
-            __syncthreads();
-            if (act) {
-                const Real* src = hb + sl * hs + s * 24;
-#pragma unroll
-                for (int k = 0; k < 24; ++k) v[k] = src[k];
-            }
-        }
-        if constexpr (REGMIX) {
-            // every lane of a row takes part (rows of inactive sites are whole
-            // rows); the coefficient loads stay after the hop, whose register
-            // peak they would otherwise raise
-            __builtin_amdgcn_sched_barrier(0);
-            const Real* tb = table + rhs * o.table_rstride;
-            constexpr bool rev0 = MIXM == MIX_AS, rev1 = MIXM != MIX_AS;  // M5: L_- reversed; M5^T: L_+^T
-            mix_reg16<Real, MIXM, rev0>(v, tb, s);
-            mix_reg16<Real, MIXM, rev1>(v + 12, tb + 6 * 16, s);
-        }
+        if constexpr (MIX)
+            mix_lds<Real, NSMAX, MIXM>(v, hb, table + rhs * o.table_rstride, Ns, nsites, sl, s, act, hs, tid, T);
+        if constexpr (REGMIX) mix_reg<Real, MIXM>(v, table + rhs * o.table_rstride, s);
         double part = 0;
         if (act) part = epi(rhs, i5, s, v);
+        if constexpr (POST) {
+            const Real* tb = table + epi.ptab + rhs * o.table_rstride;
+            if constexpr (REGMIX) {
+                mix_reg<Real, MIX_AS>(v, tb, s);
+            } else {
+                __syncthreads();  // every lane has read back its phase-2 vector
+                mix_lds<Real, NSMAX, MIX_AS>(v, hb, tb, Ns, nsites, sl, s, act, hs, tid, T);
+            }
+            if (act) epi.post(rhs, i5, s, v);
+        }
         if constexpr (Epi::kReduce) {
             double tot = block_sum(part, red);
             if (tid == 0) o.partials[(long)rhs * g.nblocks + lb] = tot;
@@ -1054,10 +1125,9 @@ struct ProLoad {
     __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const { f.load(rhs, i, s, v); }
 };
 
-// CG direction update, Algorithm 1: p = c_r r + beta p with a per-right-hand-
-// side c_r (NULL = 1).  After every iteration c_r = 1 and beta is CG's; a
-// restart sets (c_r, beta) = (1, 0) on a zeroed p (fresh Krylov space) or
-// (0, 1) (reliable update: p kept, only M5^T gamma_5 p is formed).
+// CG kernel E, for the right-hand sides that solve C C^dag w = b: the
+// direction update of Algorithm 1, p = c_r r + beta p (c_r and beta as for
+// kernel B), stored, and handed on for t1 = M5^T gamma_5 p.
 template <class FR, class FP>
 struct ProCgE {
     FR r;
@@ -1067,7 +1137,7 @@ struct ProCgE {
     template <class Real>
     __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const {
         r.sload(rhs, i, s, v);
-        const Real a = ecr ? (Real)ecr[rhs] : (Real)1;
+        const Real a = (Real)ecr[rhs];
         const Real b = (Real)beta[rhs];
         Real q[24];
         p.sload(rhs, i, s, q);
@@ -1129,18 +1199,41 @@ struct EpiLin {
     }
 };
 
-// CG kernel B: u = p - gamma_5 v (v = D^OE t2), returns |u|^2.
-template <class FP, class FU>
+// CG kernel B: the new search direction in the form u = C^dag p.  Algorithm 1
+// updates p = r + beta p; C^dag is linear, so u = C^dag p follows the same
+// recurrence, u = c_r C^dag r + beta u, with C^dag r = r - gamma_5 v
+// (v = D^OE t2, t2 = M5^T D^EO M5^T gamma_5 r) and p itself never formed.
+// c_r (ecr) is 1 after every iteration; a restart sets (c_r, beta) = (1, 0)
+// on a zeroed u (fresh Krylov space) or (0, 1) (reliable update: u kept).
+// The right-hand sides with accp[rhs] set (C C^dag w = b, whose solution
+// takes w += alpha p) form p in kernel E and t2 from it, and take
+// u = C^dag p = p - gamma_5 v directly: there the solution and the residual
+// must see the same direction, which a recurrence for u would let drift apart
+// by the rounding of the stored vectors.  Returns |u|^2 = (p, C C^dag p).
+template <class FR, class FU>
 struct EpiCgB {
     static constexpr bool kReduce = true;
-    FP p;
+    FR r;
     FU u;
+    typename FU::Ptrs p;  // laid out as u
+    const double* beta;
+    const double* ecr;
+    const int* accp;
     template <class Real>
     __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         Real w[24];
-        p.sload(rhs, i, s, w);
+        if (accp && accp[rhs]) {
+            u.with(p).sload(rhs, i, s, w);
 #pragma unroll
-        for (int k = 0; k < 24; ++k) w[k] = k < 12 ? w[k] - v[k] : w[k] + v[k];
+            for (int k = 0; k < 24; ++k) w[k] = k < 12 ? w[k] - v[k] : w[k] + v[k];
+        } else {
+            const Real a = (Real)ecr[rhs], b = (Real)beta[rhs];
+            Real rr[24];
+            r.sload(rhs, i, s, rr);
+            u.sload(rhs, i, s, w);
+#pragma unroll
+            for (int k = 0; k < 24; ++k) w[k] = a * (k < 12 ? rr[k] - v[k] : rr[k] + v[k]) + b * w[k];
+        }
         u.store(rhs, i, s, w);  // gathered by the next kernel: cached
         return norm2_24(w);
     }
@@ -1150,31 +1243,41 @@ struct EpiCgB {
 // solution takes y += alpha u (D x = b: y = C^dag w is tracked, so r is the
 // residual of C y = b''), or w += alpha p for the right-hand sides with
 // accp[rhs] set (C C^dag w = b: Algorithm 1 on A = C C^dag as printed).
+// Phase 4 then forms t1 = M5^T gamma_5 r of the new residual, the first
+// step of the next iteration's C^dag r (kernel E replaces it with
+// M5^T gamma_5 p for the right-hand sides with accp[rhs] set).
 template <class FU, class FR, class FY>
 struct EpiCgD {
     static constexpr bool kReduce = true;
+    static constexpr bool kPost = true;
     FU u;
     FR r;
     FY y;
     const double* alpha;
-    FU p;
+    typename FU::Ptrs p;   // laid out as u
     const int* accp;
+    typename FR::Ptrs t1;  // laid out as r
+    int ptab;              // the M5^T gamma_5 coefficients: kernel table + ptab
     template <class Real>
     __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         const Real a = (Real)alpha[rhs];
         Real uu[24], w[24];
         u.sload(rhs, i, s, uu);
         r.sload(rhs, i, s, w);
+        // v := the new residual (left in v for phase 4)
 #pragma unroll
-        for (int k = 0; k < 24; ++k) w[k] -= a * (uu[k] - v[k]);
-        r.sstore(rhs, i, s, w);
-        if (accp && accp[rhs]) p.sload(rhs, i, s, uu);
-        Real yy[24];
-        y.sload(rhs, i, s, yy);
+        for (int k = 0; k < 24; ++k) v[k] = w[k] - a * (uu[k] - v[k]);
+        r.sstore(rhs, i, s, v);
+        if (accp && accp[rhs]) u.with(p).sload(rhs, i, s, uu);
+        y.sload(rhs, i, s, w);
 #pragma unroll
-        for (int k = 0; k < 24; ++k) yy[k] += a * uu[k];
-        y.sstore(rhs, i, s, yy);
-        return norm2_24(w);
+        for (int k = 0; k < 24; ++k) w[k] += a * uu[k];
+        y.sstore(rhs, i, s, w);
+        return norm2_24(v);
+    }
+    template <class Real>
+    __device__ __forceinline__ void post(int rhs, long i, int s, const Real* v) const {
+        r.with(t1).store(rhs, i, s, v);  // the next kernel gathers it: cached
     }
 };
 

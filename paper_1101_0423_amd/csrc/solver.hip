@@ -9,13 +9,17 @@
 // direction p is kept across restarts), with the automatic switch to defect
 // correction when reliable updates stall (Sec. 2.3).
 //
-// One inner CG iteration is five fused stencil kernels plus two one-block
-// reduction finishers (Secs. 3.2-3.5):
-//   E: p = r + beta p;          t1 = M5^T g5 p            (odd)
-//   A: t2 = M5^T D^EO t1                                    (even)
-//   B: u  = p - g5 D^OE t2,     |u|^2 = (p, C C^dag p)     (odd)   -> alpha
-//   C: t3 = M5 D^EO u                                       (even)
-//   D: q  = u - M5 D^OE t3;  y += alpha u;  r -= alpha q;  |r|^2 (odd) -> beta
+// One inner CG iteration is four fused stencil kernels plus two one-block
+// reduction finishers (Secs. 3.2-3.5).  The search direction is carried as
+// u = C^dag p: C^dag is linear, so u follows p's recurrence p = r + beta p as
+// u = C^dag r + beta u, and p itself is never formed (it is only for the
+// solution update, which takes y += alpha u):
+//   A: t2 = M5^T D^EO t1                                            (even)
+//   B: u  = r - g5 D^OE t2 + beta u,  |u|^2 = (p, C C^dag p)        (odd) -> alpha
+//   C: t3 = M5 D^EO u                                               (even)
+//   D: q  = u - M5 D^OE t3;  y += alpha u;  r -= alpha q;  |r|^2;
+//      t1 = M5^T g5 r for the next iteration                       (odd) -> beta
+// (C^dag r = r - g5 D^OE M5^T D^EO M5^T g5 r.)
 // alpha, beta and the convergence flags never leave the device; the host
 // replays a hipGraph of four iterations and watches the live flags that the
 // finisher mirrors into mapped host memory, so that a round of replays ends
@@ -55,7 +59,7 @@ static double link_bytes(int fmt) { return fmt == LINK_D18 ? 144.0 : fmt == LINK
 double bytes_per_iter(const dwf_ctx* c, int inner_prec, int link_fmt) {
     const double sb = spinor_bytes(inner_prec);
     const double yb = inner_prec == DWF_PREC_FP64 ? 192.0 : 96.0;
-    return (double)c->V5h * (15.0 * sb + 2.0 * yb) + 4.0 * (double)c->V4h * 8.0 * link_bytes(link_fmt);
+    return (double)c->V5h * (13.0 * sb + 2.0 * yb) + 4.0 * (double)c->V4h * 8.0 * link_bytes(link_fmt);
 }
 
 // ---------------------------------------------------------------------------
@@ -164,8 +168,8 @@ enum { B_E = 0, B_O, BP_E, BP_O, BPP, YH_E, YH_O, T64_E, NF64 };
 enum { L_R = NF64, L_P, L_U, L_T1, L_T23, L_Y, NFALL };
 // per-slot masks on the device (each has its own pinned staging row)
 enum { M_SETUP = 0, M_GUESS, M_NOGUESS, M_OUTER, M_REVERT, M_RESET, M_RUFIN, M_POST, M_FINAL, M_AGAIN,
-       M_SETUP0, M_SETUP1, M_GUESS1, M_F0, M_F1, M_FIN0, M_FORM, NMASK };
-enum { LIST_INNER = 0, LIST_RUFIN, NLIST };
+       M_SETUP0, M_SETUP1, M_GUESS1, M_F0, M_F1, M_FIN0, M_FORM, M_START, NMASK };
+enum { LIST_INNER = 0, LIST_RUFIN, LIST_F1, LIST_RUF1, NLIST };
 
 constexpr int kItersPerGraph = 4;
 
@@ -384,8 +388,7 @@ class Engine : public EngineBase {
         DWF_HIP(hipEventCreate(&e1));
         hipError_t e = hipSuccess;
         auto pass = [&]() {
-            hipError_t r = kE(nullptr);
-            if (r == hipSuccess) r = kA(nullptr);
+            hipError_t r = kA(nullptr);
             if (r == hipSuccess) r = kB(nullptr);
             if (r == hipSuccess) r = kC(nullptr);
             if (r == hipSuccess) r = kD(nullptr);
@@ -469,7 +472,9 @@ class Engine : public EngineBase {
     int* hlist[NLIST] = {};
     const int* cur_list = nullptr;  // list and group count the inner kernels launch over
     int cur_ng = 0;
-    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;  // by group count
+    int cur_ng1 = 0;  // groups of the C C^dag w = b slots of the list (kernel E)
+    // by group counts of the slot list and of its C C^dag w = b slots
+    std::map<long, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     void* pin = nullptr;
     double* hd = nullptr;  // rr, uu, alpha, beta, rr_target, aux, ecr  (K each)
     int* hi = nullptr;     // live, iters, status, maxiter  (K each), then the masks
@@ -656,10 +661,18 @@ class Engine : public EngineBase {
     }
 
     // inner CG kernels
-    hipError_t kE(const int* live) {
+    // T: t1 = M5^T g5 r, once at the start of an inner cycle (afterwards
+    // kernel D forms it for the next iteration)
+    hipError_t kT(const int* live) {
+        return launch_dwf<Real, F, LF, false, MIX_AS, ProLoad<F>, EpiStore<F>>(
+            glo(1), lo(L_R), lk[1], slo(ST_M5TG5), ProLoad<F>{lo(L_R)}, EpiStore<F>{lo(L_T1)}, kopt_in(live, false), s);
+    }
+    // E: p = c_r r + beta p, t1 = M5^T g5 p for the slots of list l (those
+    // that solve C C^dag w = b), in ng groups
+    hipError_t kE(const int* live, int l, int ng) {
         return launch_dwf<Real, F, LF, false, MIX_AS, ProCgE<F, F>, EpiStore<F>>(
             glo(1), lo(L_R), lk[1], slo(ST_M5TG5), ProCgE<F, F>{lo(L_R), lo(L_P), w.st.beta, w.st.ecr},
-            EpiStore<F>{lo(L_T1)}, kopt_in(live, false), s);
+            EpiStore<F>{lo(L_T1)}, KOpt{live, nullptr, K, TS, kgroup, dlist[l], ng}, s);
     }
     hipError_t kA(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_AS, ProLoad<F>, EpiStore<F>>(
@@ -667,8 +680,8 @@ class Engine : public EngineBase {
     }
     hipError_t kB(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_NONE, ProLoad<F>, EpiCgB<F, F>>(
-            glo(1), lo(L_T23), lk[1], nullptr, ProLoad<F>{lo(L_T23)}, EpiCgB<F, F>{lo(L_P), lo(L_U)}, kopt_in(live, true),
-            s);
+            glo(1), lo(L_T23), lk[1], nullptr, ProLoad<F>{lo(L_T23)},
+            EpiCgB<F, F>{lo(L_R), lo(L_U), lo(L_P).ptrs(), w.st.beta, w.st.ecr, dmask[M_FORM]}, kopt_in(live, true), s);
     }
     hipError_t kC(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiStore<F>>(
@@ -677,12 +690,14 @@ class Engine : public EngineBase {
     hipError_t kD(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiCgD<F, F, FY>>(
             glo(1), lo(L_T23), lk[1], slo(ST_M5), ProLoad<F>{lo(L_T23)},
-            EpiCgD<F, F, FY>{lo(L_U), lo(L_R), ylo(), w.st.alpha, lo(L_P), dmask[M_FORM]}, kopt_in(live, true), s);
+            EpiCgD<F, F, FY>{lo(L_U), lo(L_R), ylo(), w.st.alpha, lo(L_P).ptrs(), dmask[M_FORM], lo(L_T1).ptrs(),
+                             (int)(slo(ST_M5TG5) - slo(ST_M5))},
+            kopt_in(live, true), s);
     }
     hipError_t iteration() {
         hipError_t e;
         const int* live = w.st.live;
-        if ((e = kE(live)) != hipSuccess) return e;
+        if (cur_ng1 && (e = kE(live, LIST_F1, cur_ng1)) != hipSuccess) return e;
         if ((e = kA(live)) != hipSuccess) return e;
         if ((e = kB(live)) != hipSuccess) return e;
         if ((e = fin(glo(1).nblocks, FIN_ALPHA)) != hipSuccess) return e;
@@ -694,7 +709,8 @@ class Engine : public EngineBase {
     // node by node (no stream capture); cached per group count.  The nodes read
     // the slot list and the CG state on the device, so replays need no update.
     int graph_for(hipGraphExec_t* out) {
-        auto it = graphs.find(cur_ng);
+        const long key = (long)cur_ng * (K + 1) + cur_ng1;
+        auto it = graphs.find(key);
         if (it != graphs.end()) {
             *out = it->second.second;
             return DWF_OK;
@@ -715,7 +731,7 @@ class Engine : public EngineBase {
             (void)hipGraphDestroy(b.graph);
             return fail(DWF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         }
-        graphs[cur_ng] = {b.graph, ex};
+        graphs[key] = {b.graph, ex};
         *out = ex;
         return DWF_OK;
     }
@@ -878,8 +894,8 @@ class Engine : public EngineBase {
             h_status(r) = 0;
             h_maxiter(r) = q.p.maxiter;
             // p := r on the first cycle, in defect correction and after a
-            // rejected cycle (p zeroed below, c_r = 1, beta = 0); reliable
-            // updates keep p (c_r = 0, beta = 1)
+            // rejected cycle (u = C^dag p and p zeroed below, c_r = 1,
+            // beta = 0); reliable updates keep p (c_r = 0, beta = 1)
             const bool reset = q.cycles == 0 || !q.mode_ru || q.reverted;
             h_ecr(r) = reset ? 1.0 : 0.0;
             h_beta(r) = reset ? 0.0 : 1.0;
@@ -899,8 +915,16 @@ class Engine : public EngineBase {
         }
         if (nres) {
             DWF_HIP(hipMemcpyAsync(dmask[M_RESET], hmask[M_RESET], (size_t)K * sizeof(int), hipMemcpyHostToDevice, s));
+            CKE(half_zero(c, w.f(L_U), K, s, dmask[M_RESET]));
             CKE(half_zero(c, w.f(L_P), K, s, dmask[M_RESET]));
         }
+        // t1 = M5^T g5 r of the new residual, for every slot that starts a cycle
+        // (a kept direction multiplies it by c_r = 0: it must be finite)
+        if (upload_mask(M_START, [&](int r) { return hmask[M_OUTER][r] && sl[r].phase == PH_INNER; })) {
+            CKU();
+            CKE(kT(dmask[M_START]));
+        }
+        CKU();
         return DWF_OK;
     }
 
@@ -974,8 +998,11 @@ class Engine : public EngineBase {
                 check = check ? std::min(check, sl[r].p.check_every) : sl[r].p.check_every;
         const int cap = check ? std::max(1, (check + kItersPerGraph - 1) / kItersPerGraph) : replay_cap;
         const int nl = upload_list(LIST_INNER, [&](int r) { return sl[r].phase == PH_INNER; });
+        const int n1 =
+            upload_list(LIST_F1, [&](int r) { return sl[r].phase == PH_INNER && sl[r].form == DWF_SYSTEM_CCDAG; });
         CKU();
         use_list(LIST_INNER, nl);
+        cur_ng1 = (n1 + kgroup - 1) / kgroup;
         volatile int* lh = (volatile int*)live_pin;
         for (int r = 0; r < K; ++r) lh[r] = sl[r].phase == PH_INNER ? 1 : 0;
         hipGraphExec_t ex = nullptr;
@@ -1006,6 +1033,7 @@ class Engine : public EngineBase {
             if (ended) break;
         }
         cur_list = nullptr;
+        cur_ng1 = 0;
         if (rc) return rc;
         int nlive = 0;
         for (int r = 0; r < K; ++r) nlive += sl[r].phase == PH_INNER;
@@ -1037,19 +1065,28 @@ class Engine : public EngineBase {
         return DWF_OK;
     }
 
-    // the slots whose inner cycle ended: finish p for reliable updates,
-    // keep yhat (backup), yhat += y
+    // the slots whose inner cycle ended: finish the direction for reliable
+    // updates, keep yhat (backup), yhat += y
     int post_cycle() {
         int nfin = upload_mask(M_RUFIN, [&](int r) {
             return sl[r].phase == PH_INNER && !h_live(r) && sl[r].mode_ru && h_status(r) == 1;
         });
         CKU();
         // reliable updates: the last direction update p = r + beta p
-        // (Algorithm 1 computes p_{k+1} before testing convergence)
+        // (Algorithm 1 computes p_{k+1} before testing convergence), as
+        // u = C^dag r + beta u from the t1 = M5^T g5 r that kernel D left, or
+        // (C C^dag w = b) p itself by kernel E, whose next cycle forms u
         if (nfin) {
             use_list(LIST_RUFIN, upload_list(LIST_RUFIN, [&](int r) { return hmask[M_RUFIN][r] != 0; }));
+            const int n1 = upload_list(
+                LIST_RUF1, [&](int r) { return hmask[M_RUFIN][r] != 0 && sl[r].form == DWF_SYSTEM_CCDAG; });
             CKU();
-            hipError_t e = kE(dmask[M_RUFIN]);
+            hipError_t e = hipSuccess;
+            if (n1) e = kE(dmask[M_RUFIN], LIST_RUF1, (n1 + kgroup - 1) / kgroup);
+            if (n1 < nfin) {
+                if (e == hipSuccess) e = kA(dmask[M_RUFIN]);
+                if (e == hipSuccess) e = kB(dmask[M_RUFIN]);
+            }
             cur_list = nullptr;
             CKE(e);
         }
@@ -1077,38 +1114,41 @@ class Engine : public EngineBase {
 
 template <class Real, class F, class FY, class LF>
 int Engine<Real, F, FY, LF>::time_kernels(int launches, double* ms, double* bytes) {
-    // all kernels forced on (live = NULL); A and C are idempotent, B, D and E
+    // all kernels forced on (live = NULL); T, A and C are idempotent, B and D
     // update their outputs from finite inputs
     auto runk = [&](int k) -> hipError_t {
         switch (k) {
-            case 0: return kE(nullptr);
+            case 0: return kT(nullptr);
             case 1: return kA(nullptr);
             case 2: return kB(nullptr);
             case 3: return kC(nullptr);
             default: return kD(nullptr);
         }
     };
-    // The five kernels run in iteration order (E A B C D), so each finds the
-    // caches as an iteration leaves them; one event pair around every launch,
-    // so the averages are the kernels' own device time.
+    // One iteration's kernels (A B C D) run back to back `launches` times, so
+    // that each finds the caches as the iteration before leaves them, then T
+    // (once per cycle in a solve) `launches` times; one event pair around
+    // every launch, so the averages are the kernels' own device time.
     const int nk = 5;
     std::vector<hipEvent_t> ev(2 * (size_t)launches * nk, nullptr);
     for (auto& e : ev) DWF_HIP(hipEventCreate(&e));
     const double sb = spinor_bytes(prec) * (double)c->V5h * K;
     const double yb = (prec == DWF_PREC_FP64 ? 192.0 : 96.0) * (double)c->V5h * K;
     const double lb = (double)c->V4h * 8.0 * link_bytes(link_fmt);
-    const double model[5] = {4 * sb, 2 * sb + lb, 3 * sb + lb, 2 * sb + lb, 4 * sb + 2 * yb + lb};
+    const double model[5] = {2 * sb, 2 * sb + lb, 4 * sb + lb, 2 * sb + lb, 5 * sb + 2 * yb + lb};
     int result = DWF_OK;
     hipError_t e = hipSuccess;
-    for (int k = 0; k < nk && e == hipSuccess; ++k) e = runk(k);  // warm-up iteration
+    for (int k = 0; k < nk && e == hipSuccess; ++k) e = runk(k);  // warm-up
+    auto timed = [&](int i, int k) {
+        const size_t j = 2 * ((size_t)i * nk + k);
+        e = hipEventRecord(ev[j], s);
+        if (e == hipSuccess) e = runk(k);
+        if (e == hipSuccess) e = hipEventRecord(ev[j + 1], s);
+    };
     for (int i = 0; i < launches && e == hipSuccess; ++i)
-        for (int k = 0; k < nk && e == hipSuccess; ++k) {
-            const size_t j = 2 * ((size_t)i * nk + k);
-            e = hipEventRecord(ev[j], s);
-            if (e == hipSuccess) e = runk(k);
-            if (e == hipSuccess) e = hipEventRecord(ev[j + 1], s);
-        }
-    if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+        for (int k = 1; k < nk && e == hipSuccess; ++k) timed(i, k);
+    for (int i = 0; i < launches && e == hipSuccess; ++i) timed(i, 0);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[2 * ((size_t)(launches - 1) * nk) + 1]);
     for (int k = 0; k < nk && e == hipSuccess; ++k) {
         double tot = 0;
         for (int i = 0; i < launches && e == hipSuccess; ++i) {

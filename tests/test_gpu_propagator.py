@@ -110,7 +110,12 @@ def test_host_groups_and_device_form_agree():
 @pytest.mark.timeout(300)
 def test_full_size_mass_is_additive():
     """16^3x32, Ns = 16 (the benchmark's operator): S(mq) eta and
-    S(0) (eta - kappa S(mq) eta) agree to the solve bar."""
+    S(0) (eta - kappa S(mq) eta) agree to the solve bar.  The property is
+    exact; what separates the two sides is the forward error of two solves,
+    one of them with the massless operator, whose conditioning turns a 1e-10
+    residual into forward errors up to about 1e-8 (measured 0.6e-8 and
+    1.3e-8 for two CG iteration paths).  Both solves therefore run to a
+    1e-12 residual, which leaves the 1e-8 bar a margin of 10 or more."""
     import paper_1101_0423_amd as dwf
     P = Problem.workload("odwf_16x16x16x32_ns16")
     eta = gaussian_4d(P.dims, 8, 1)[0]
@@ -118,9 +123,9 @@ def test_full_size_mass_is_additive():
     c1 = P.context()
     c0 = dwf.Context(P.U, P.dims, P.ns, P.m0, 0.0, P.sigma, P.omega)
     try:
-        s1, st1, rc1 = c1.propagator(eta)
+        s1, st1, rc1 = c1.propagator(eta, tol=1e-12)
         assert rc1 == dwf.DWF_OK, st1
-        s0, st0, rc0 = c0.propagator(eta - kappa * s1)
+        s0, st0, rc0 = c0.propagator(eta - kappa * s1, tol=1e-12)
         assert rc0 == dwf.DWF_OK, st0
     finally:
         c1.close()
