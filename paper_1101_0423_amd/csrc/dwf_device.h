@@ -879,6 +879,15 @@ __device__ __forceinline__ void mix_reg16(Real* v, const Real* __restrict__ C, i
 // and shared by the Ns slices (and by every right-hand side).
 // ---------------------------------------------------------------------------
 
+// A prologue or epilogue with set_ns(n) sets the component-block stride of
+// its fields (kernels at Ns = 16 make it a compile-time constant).
+template <class T>
+__device__ __forceinline__ auto set_ns16(T& t, int) -> decltype(t.set_ns(16L)) {
+    t.set_ns(16L);
+}
+template <class T>
+__device__ __forceinline__ void set_ns16(T&, long) {}
+
 // An epilogue with a second output: kPost = true, a member ptab (the offset
 // of the M5^T gamma_5 coefficients from the kernel's table, indexed per
 // right-hand side in the same way) and post(rhs, i, s, v), which stores
@@ -989,15 +998,27 @@ template <class F, class E> struct HopPipe {
 
 template <class Real, class F, class LF, int NSMAX, bool HOP, int MIXM, bool REGMIX, class Pro, class Epi>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<F, FS>::value ? 4 : 1)))
-k_dwf(Geom g, F in, LF links, const Real* __restrict__ table, Pro pro, Epi epi, KOpt o) {
+k_dwf(Geom g, F in0, LF links, const Real* __restrict__ table, Pro pro0, Epi epi0, KOpt o) {
     // REGMIX: Ns == 16, M5 / M5^T applied in registers (no LDS transpose)
     constexpr bool MIX = MIXM != MIX_NONE && !REGMIX;
+    // At Ns = 16 the slices of a component block lie 16 vectors apart in
+    // every field; with that stride a constant, the vector loads and stores
+    // of a site share one address (immediate offsets) and the index
+    // arithmetic folds.
+    F in = in0;
+    Pro pro = pro0;
+    Epi epi = epi0;
+    if constexpr (REGMIX) {
+        in.ns = 16;
+        set_ns16(pro, 0);
+        set_ns16(epi, 0);
+    }
     // phase 4 runs in the same way as phase 2 (registers or LDS)
     constexpr bool POST = EpiPost<Epi>::value;
     static_assert(!POST || MIXM == MIX_SA || MIXM == MIX_AS, "phase 4 needs a kernel with a structured phase 2");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int LS = LdsLink<Real>::STR;
-    const int Ns = g.Ns;
+    const int Ns = REGMIX ? 16 : g.Ns;
     const int tid = threadIdx.x, T = blockDim.x;
 
     // workgroup -> (group of right-hand sides, lattice block)
@@ -1121,6 +1142,7 @@ struct CgState {
 template <class F>
 struct ProLoad {
     F f;
+    __device__ __forceinline__ void set_ns(long n) { f.ns = n; }
     template <class Real>
     __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const { f.load(rhs, i, s, v); }
 };
@@ -1134,6 +1156,7 @@ struct ProCgE {
     FP p;
     const double* beta;
     const double* ecr;
+    __device__ __forceinline__ void set_ns(long n) { r.ns = p.ns = n; }
     template <class Real>
     __device__ __forceinline__ void operator()(int rhs, long i, int s, Real* v) const {
         r.sload(rhs, i, s, v);
@@ -1163,6 +1186,7 @@ template <class F, bool RED = false>
 struct EpiStore {
     static constexpr bool kReduce = RED;
     F out;
+    __device__ __forceinline__ void set_ns(long n) { out.ns = n; }
     template <class Real>
     __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         out.store(rhs, i, s, v);  // the next kernel gathers it: cached
@@ -1219,6 +1243,7 @@ struct EpiCgB {
     const double* beta;
     const double* ecr;
     const int* accp;
+    __device__ __forceinline__ void set_ns(long n) { r.ns = u.ns = n; }
     template <class Real>
     __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         Real w[24];
@@ -1258,6 +1283,7 @@ struct EpiCgD {
     const int* accp;
     typename FR::Ptrs t1;  // laid out as r
     int ptab;              // the M5^T gamma_5 coefficients: kernel table + ptab
+    __device__ __forceinline__ void set_ns(long n) { u.ns = r.ns = y.ns = n; }
     template <class Real>
     __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
         const Real a = (Real)alpha[rhs];
