@@ -146,18 +146,47 @@ def summarize_rocpd(path):
     db = sqlite3.connect(path)
     tabs = {r[0] for r in db.execute("select name from sqlite_master")}
     if "pmc_events" in tabs and db.execute("select count(*) from pmc_events").fetchone()[0] > 0:
-        rows = db.execute("select name, counter_name, count(*), avg(counter_value), avg(duration) "
-                          "from pmc_events group by name, counter_name order by avg(duration) desc").fetchall()
-        print(f"{'kernel':40s} {'counter':12s} {'dispatches':>10s} {'avg value':>14s} {'avg us':>9s}")
-        for name, ctr, n, val, dur in rows:
-            print(f"{kernel_label(name):40s} {ctr:12s} {n:10d} {val:14.1f} {dur / 1e3:9.1f}")
+        # averages over the full dispatches (at least half as long as the
+        # kernel's longest): a dispatch of stopped right-hand sides exits at once
+        by = {}
+        for name, ctr, val, dur in db.execute("select name, counter_name, counter_value, duration from pmc_events"):
+            by.setdefault((kernel_label(name), ctr), []).append((dur, val))
+        print(f"{'kernel':40s} {'counter':12s} {'dispatches':>10s} {'full':>5s} {'avg value (full)':>17s} "
+              f"{'avg us (full)':>14s}")
+        for (k, ctr), v in sorted(by.items(), key=lambda kv: -max(d for d, _ in kv[1])):
+            full = [(d, x) for d, x in v if d >= 0.5 * max(d for d, _ in v)]
+            print(f"{k[:40]:40s} {ctr:12s} {len(v):10d} {len(full):5d} {sum(x for _, x in full) / len(full):17.1f} "
+                  f"{sum(d for d, _ in full) / len(full) / 1e3:14.1f}")
         return
-    rows = db.execute("select name, count(*), sum(duration), avg(duration) from kernels "
-                      "group by name order by sum(duration) desc").fetchall()
-    tot = sum(r[2] for r in rows)
-    print(f"{'kernel':40s} {'calls':>8s} {'total ms':>10s} {'avg us':>9s} {'share':>6s}")
-    for name, n, s, a in rows[:20]:
-        print(f"{kernel_label(name):40s} {n:8d} {s / 1e6:10.2f} {a / 1e3:9.2f} {100 * s / tot:5.1f}%")
+    import statistics
+    trace = [(kernel_label(n), s, e) for n, s, e in
+             db.execute("select name, start, end from kernels order by start").fetchall()]
+    by = {}
+    for k, s, e in trace:
+        by.setdefault(k, []).append(e - s)
+    tot = sum(sum(v) for v in by.values())
+    # "full": dispatches at least half as long as the kernel's longest; a
+    # dispatch whose right-hand sides have all stopped exits at once
+    print(f"{'kernel':40s} {'calls':>8s} {'total ms':>10s} {'avg us':>9s} {'full':>6s} {'median us':>10s} "
+          f"{'share':>6s}")
+    for k, v in sorted(by.items(), key=lambda kv: -sum(kv[1]))[:20]:
+        full = [d for d in v if d >= 0.5 * max(v)]
+        print(f"{k[:40]:40s} {len(v):8d} {sum(v) / 1e6:10.2f} {statistics.mean(v) / 1e3:9.2f} {len(full):6d} "
+              f"{statistics.median(full) / 1e3:10.2f} {100 * sum(v) / tot:5.1f}%")
+    # inner iterations inside the solves: A B finish C D finish, followed by A
+    pat = ["hop_eo_m5t", "hop_oe_g5_dir", "finish_reduction", "hop_eo_m5", "hop_oe_m5_cgupd_m5t",
+           "finish_reduction"]
+    its = [i for i in range(len(trace) - 6)
+           if [trace[i + j][0] for j in range(7)] == pat + ["hop_eo_m5t"]]
+    if its:
+        longest = max(trace[i][2] - trace[i][1] for i in its)
+        its = [i for i in its if trace[i][2] - trace[i][1] >= 0.5 * longest]
+        per = statistics.median(trace[i + 6][1] - trace[i][1] for i in its)
+        busy = statistics.median(sum(trace[i + j][2] - trace[i + j][1] for j in range(6)) for i in its)
+        print(f"\ninner iterations inside the solves ({len(its)} with every kernel live): median period "
+              f"{per / 1e3:.2f} us start to start, kernels busy {busy / 1e3:.2f} us of it")
+        for j, k in enumerate(pat):
+            print(f"  {k:24s} median {statistics.median(trace[i + j][2] - trace[i + j][1] for i in its) / 1e3:8.2f} us")
 
 
 def _ctx(dwf, U, w, **kw):
@@ -489,12 +518,22 @@ def main():
         dst = torch.empty_like(src)
         side = torch.cuda.Stream()  # the library never uses the legacy null stream
         torch.cuda.synchronize()
+        copy_gbs = {}
         for nt in (False, True):
+            t = []
             for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(side)
                 dwf.stream_copy(src, dst, nontemporal=nt, stream=side.cuda_stream)
+                e1.record(side)
+                e1.synchronize()
+                t.append(e0.elapsed_time(e1) * 1e-3)
+            # bytes read plus bytes written, per second, median of three
+            copy_gbs["nontemporal" if nt else "cached"] = round(2 * n / sorted(t)[1] * 1e-9, 1)
         del src, dst
         print(json.dumps(dict(mode="kernels", workload=wname, ms={k: ms[k] for k in ms},
-                              bytes={k: by[k] for k in by}, copy_bytes_read=n, copy_bytes_written=n)), flush=True)
+                              bytes={k: by[k] for k in by}, copy_bytes_read=n, copy_bytes_written=n,
+                              copy_read_plus_write_gbs=copy_gbs)), flush=True)
         ctx.close()
         return
 

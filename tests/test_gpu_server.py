@@ -21,6 +21,9 @@ pytestmark = pytest.mark.gpu
 TOL_RES = 1e-10
 TOL_FWD = 1e-8
 SMALL = Problem.workload("shamir_4x4x4x4_ns8")
+# a second field of the same shape and operator parameters (another gauge seed)
+_w = inp.workload("shamir_4x4x4x4_ns8")
+SMALL2 = Problem(_w["dims"], _w["ns"], _w["m0"], _w["mq"], _w["sigma"], _w["omega"], _w["eps"], 4711, 4712)
 _rng = np.random.default_rng(191)
 RAGGED = Problem((4, 6, 2, 8), 5, 1.6, 0.1, _rng.uniform(0.2, 1.4, 5), _rng.uniform(0.5, 1.5, 5), 0.5, 51, 52,
                  antiperiodic=True)
@@ -51,20 +54,26 @@ def true_res(P, mq, b, x):
 
 
 def test_mixed_masses_each_equals_alone():
+    """Requests on three resident fields at once (two of the same shape, one
+    ragged), several masses each: every result equals its solve alone."""
     import paper_1101_0423_amd as dwf
-    print("[server] 4^4x8 + ragged, masses", MASSES, flush=True)
+    print("[server] 4^4x8 (two fields) + ragged, masses", MASSES, flush=True)
     dwf.server_stats(reset=True)
-    cs, cr = SMALL.context(), RAGGED.context()
+    cs, cs2, cr = SMALL.context(), SMALL2.context(), RAGGED.context()
     try:
         jobs = []
         for k in range(8):
             mq = MASSES[k % len(MASSES)]
             b = rhs(SMALL, k)
             jobs.append((SMALL, mq, b, cs.submit(b, mq=mq)))
+        for k in range(4):
+            mq = MASSES[(k + 1) % len(MASSES)]
+            b = rhs(SMALL2, 50 + k)
+            jobs.append((SMALL2, mq, b, cs2.submit(b, mq=mq)))
         for k in range(2):
             b = rhs(RAGGED, 100 + k)
             jobs.append((RAGGED, RAGGED.mq, b, cr.submit(b)))
-        shape = {id(SMALL): cs.spinor_shape(), id(RAGGED): cr.spinor_shape()}
+        shape = {id(SMALL): cs.spinor_shape(), id(SMALL2): cs2.spinor_shape(), id(RAGGED): cr.spinor_shape()}
         out = []
         for P, mq, b, t in jobs:
             rc, x, st = wait(t, shape[id(P)])
@@ -80,6 +89,7 @@ def test_mixed_masses_each_equals_alone():
         assert s["busy_seconds"] > 0
     finally:
         cs.close()
+        cs2.close()
         cr.close()
     # each request alone, through dwf_solve on a context with its mass
     for P, mq, b, x in out:
