@@ -4,9 +4,10 @@ A solve capped at k inner iterations (defect correction, so that the first
 cycle runs k plain CG iterations from zero with p = r, Algorithm 1) returns
 the reconstruction of its k-th iterate (Eq. (10)).  The oracle's solve capped
 at k iterations returns the same quantity in FP64, so the two differ only by
-the rounding of the low-precision inner kernels E, A, B, C, D (with the
-fifth-dimension recurrences, the 12-real or 18-real links, the fused CG
-updates and the two reductions): unlike a converged solve, whose FP64 defect
+the rounding of the low-precision inner kernels T, A, B, C, D (with the
+fifth-dimension recurrences in registers at Ns = 16 and through LDS at
+Ns = 5, 12, 32, the 12-real or 18-real links, the fused CG updates and the
+two reductions): unlike a converged solve, whose FP64 defect
 correction would absorb an error of the inner operator, this comparison sees
 it directly.  (The oracle's truncated iterates are pinned to the Krylov
 minimisation property of CG in the oracle's own pins.)
@@ -15,9 +16,12 @@ Bars, element-wise max|x - x_o| / max|x_o| (the norm-wise error is held to
 the same bar), for k = 1, 2, 5: FP64 1e-13, FP32 1.5e-6 (12-real and 18-real
 links), FP16 storage 3e-3.  A rounding perturbation can grow over CG steps
 (alpha and beta are ratios of reductions of perturbed vectors); measured, it
-barely does over these k: FP32 2.6e-7 -> 4.5e-7 element-wise from k = 1 to 5
-at 16^3x32x16 (1.3e-7 -> 3.0e-7 norm-wise), FP16 8.2e-4 -> 1.0e-3, FP64 at
-most 6.3e-15 (printed by each case), so the bars leave a factor 3 or more.
+barely does over these k: FP32 2.6e-7 -> 4.4e-7 element-wise from k = 1 to 5
+at 16^3x32x16, at most 6.9e-7 at Ns = 32; FP16 8.2e-4 -> 1.1e-3 at
+16^3x32x16, at most 1.9e-3 at Ns = 32, where every iteration rounds twice as
+many slices through the fifth-dimension recurrences (binary16 keeps 11 bits:
+about 20 stores of each site's vectors by k = 5 give a random-walk bound of
+sqrt(20) 2^-11 = 2.2e-3); FP64 at most 6.3e-15 (printed by each case).
 """
 import numpy as np
 import pytest
@@ -34,6 +38,12 @@ PROBS = {
     # ragged workgroups, Ns = 5, sigma != omega, antiperiodic time
     "ragged": lambda: Problem((4, 6, 2, 8), 5, 1.6, 0.1, _rng.uniform(0.2, 1.4, 5), _rng.uniform(0.5, 1.5, 5),
                               0.5, 61, 62, antiperiodic=True),
+    # the two other fifth-dimension paths of the kernels through LDS: Ns = 12
+    # (a 16-slot template, below a full DPP row) and Ns = 32 (the 32-slot one)
+    "ns12": lambda: Problem((4, 4, 4, 8), 12, 1.8, 0.05, _rng.uniform(0.2, 1.4, 12), _rng.uniform(0.5, 1.5, 12),
+                            0.5, 65, 66),
+    "ns32": lambda: Problem((4, 4, 2, 8), 32, 1.8, 0.05, *(2 * [_rng.uniform(0.5, 1.5, 32)]), 0.5, 67, 68,
+                            antiperiodic=True),
 }
 # inner precision, link_compress (-1: the library's default, 12-real for an SU(3) field)
 PRECS = {"fp64": (0, -1), "fp32-12real": (1, 1), "fp32-18real": (1, 0), "fp16": (2, -1)}
