@@ -464,7 +464,7 @@ def main():
     ap.add_argument("--kernel-launches", type=int, default=20)
     ap.add_argument("--mode", choices=["solve", "kernels", "batch", "serve"], default="solve",
                     help="kernels: one short solve without graphs, then each inner kernel timed "
-                         "(the driver for counter runs); batch: 12 point sources on 24^3x48, Ns=16, "
+                         "(the program the counter runs profile); batch: 12 point sources on 24^3x48, Ns=16, "
                          "batched vs sequential; serve: Poisson request stream, served vs FIFO")
     ap.add_argument("--nrhs", type=int, default=12, help="batch mode: right-hand sides")
     ap.add_argument("--requests", type=int, default=200, help="serve mode: requests in the stream")

@@ -6,7 +6,7 @@ the reconstruction of its k-th iterate (Eq. (10)).  The oracle's solve capped
 at k iterations returns the same quantity in FP64, so the two differ only by
 the rounding of the low-precision inner kernels T, A, B, C, D (with the
 fifth-dimension recurrences in registers at Ns = 16 and through LDS at
-Ns = 5, 12, 32, the 12-real or 18-real links, the fused CG updates and the
+Ns = 1, 2, 5, 12, 32, the 12-real or 18-real links, the fused CG updates and the
 two reductions): unlike a converged solve, whose FP64 defect
 correction would absorb an error of the inner operator, this comparison sees
 it directly.  (The oracle's truncated iterates are pinned to the Krylov
@@ -44,6 +44,10 @@ PROBS = {
                             0.5, 65, 66),
     "ns32": lambda: Problem((4, 4, 2, 8), 32, 1.8, 0.05, *(2 * [_rng.uniform(0.5, 1.5, 32)]), 0.5, 67, 68,
                             antiperiodic=True),
+    # the degenerate fifth dimensions: one slice (M5 is a number per
+    # chirality) and two
+    "ns1": lambda: Problem((4, 4, 2, 4), 1, 1.2, 0.3, [0.7], [1.3], 0.5, 69, 70),
+    "ns2": lambda: Problem((4, 2, 4, 4), 2, 1.5, 0.1, [0.6, 1.1], [1.2, 0.8], 0.5, 71, 72),
 }
 # inner precision, link_compress (-1: the library's default, 12-real for an SU(3) field)
 PRECS = {"fp64": (0, -1), "fp32-12real": (1, 1), "fp32-18real": (1, 0), "fp16": (2, -1)}
