@@ -271,8 +271,69 @@ def run_batch(nrhs=12, log=True):
                 rhs_per_workgroup=st_b[0]["rhs_per_block"], kernels=kern)
 
 
+def run_batch_small(nrhs=12, reps=3, log=True):
+    """8^3 x 16, Ns = 16, 12 Gaussian sources: the batched form where one
+    solve is too small to fill the GPU.  Median of reps batched solves against
+    the median of reps rounds of 12 single solves; every true residual from the
+    solver's FP64 check."""
+    import torch
+
+    import dwf_inputs as inp
+    import paper_1101_0423_amd as dwf
+
+    wname = "odwf_8x8x8x16_ns16_12rhs"
+    w = inp.workload(wname)
+    dims, ns = w["dims"], w["ns"]
+    U = inp.gauge_field(dims, w["eps"], seed=w["seed_gauge"])
+    torch.cuda.set_device(0)
+    ctx = _ctx(dwf, U, w)
+    B = torch.from_numpy(inp.gaussian_spinor(dims, ns, seed=w["seed_rhs"], nrhs=nrhs)).cuda()
+    X = torch.zeros_like(B)
+    X1 = torch.zeros_like(B[0])
+    params = dwf.default_params(inner_prec=1, tol=1e-10)
+    ctx.solve_dev(B, X, nrhs=nrhs, params=params)  # engines, tuning and graphs outside the timing
+    ctx.solve_dev(B[0], X1, nrhs=1, params=params)
+    tb, ts, stb, sts = [], [], None, []
+    for _ in range(reps):
+        X.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stb, rcb = ctx.solve_dev(B, X, nrhs=nrhs, params=params)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        t = 0.0
+        sts = []
+        for k in range(nrhs):
+            X1.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, rc = ctx.solve_dev(B[k], X1, nrhs=1, params=params)
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            sts.append((st[0], rc))
+        ts.append(t)
+    diff = float(torch.linalg.vector_norm(X[nrhs - 1] - X1) / torch.linalg.vector_norm(X1))
+    ctx.close()
+    del B, X, X1
+    torch.cuda.empty_cache()
+    t_b, t_s = sorted(tb)[reps // 2], sorted(ts)[reps // 2]
+    if log:
+        print(f"[bench] small batched {nrhs}: {t_b:.3f} s vs {t_s:.3f} s sequential", file=sys.stderr, flush=True)
+    return dict(workload=f"{wname}: 8^3x16 lattice, Ns=16, m0=1.8, mq=0.01, sigma=omega~U[0.5,1.5], SU(3) links "
+                         f"eps=0.5, {nrhs} Gaussian sources, tol 1e-10, FP32 inner / FP64 outer",
+                nrhs=nrhs, seconds=round(t_b, 4), sequential_seconds=round(t_s, 4),
+                solves_per_s=round(nrhs / t_b, 2), sequential_solves_per_s=round(nrhs / t_s, 2),
+                speedup=round(t_s / t_b, 3), timing=f"median of {reps} batched solves and of {reps} rounds of "
+                                                      f"{nrhs} single solves",
+                converged=all(s["status"] == 0 for s in stb) and all(rc == 0 for _, rc in sts),
+                max_true_residual=max(s["true_residual"] for s in stb),
+                batch_vs_single_rel_diff_last=diff, iters=[s["iters"] for s in stb],
+                rhs_per_workgroup=stb[0]["rhs_per_block"])
+
+
 def batch_bench(args):
     r = run_batch(args.nrhs)
+    r["small_lattice"] = run_batch_small(args.nrhs)
     line = dict(metric="batched solves/s (24^3x48, Ns=16, 12 point sources)", value=r["solves_per_s"],
                 unit="solves/s", n_gpus=1, steps=1, warmup=1, ms_per_step=round(r["seconds"] * 1e3, 1),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32 inner / f64 outer",
@@ -574,6 +635,8 @@ def main():
     if args.prec == "fp32" and not args.no_extra:
         say("[bench] batched form: 24^3x48, 12 point sources")
         line["batched"] = run_batch(12)
+        say("[bench] batched form on a small lattice: 8^3x16, 12 sources")
+        line["batched"]["small_lattice"] = run_batch_small(12)
     if args.serve_requests > 0:
         say(f"[bench] served stream of {args.serve_requests} requests")
         sv = run_serve(args.serve_requests, 0.8)

@@ -138,7 +138,7 @@ def uniform_weights(ns, lo, hi, seed):
 
 
 # ---------------------------------------------------------------------------
-# The five workloads (operator parameters and seeds), as plain data.
+# The workloads (operator parameters and seeds), as plain data.
 # ---------------------------------------------------------------------------
 
 def workload(name):
@@ -157,6 +157,13 @@ def workload(name):
         return dict(dims=(16, 16, 16, 32), ns=ns, m0=1.8, mq=0.01,
                     sigma=w.copy(), omega=w.copy(), eps=0.5,
                     seed_gauge=SEED_GAUGE + 1, seed_rhs=SEED_RHS + 1)
+    if name == "odwf_8x8x8x16_ns16_12rhs":
+        # a lattice small enough that one solve leaves most of the GPU idle
+        ns = 16
+        w = uniform_weights(ns, 0.5, 1.5, seed=SEED_GAUGE + 105)
+        return dict(dims=(8, 8, 8, 16), ns=ns, m0=1.8, mq=0.01,
+                    sigma=w.copy(), omega=w.copy(), eps=0.5,
+                    seed_gauge=SEED_GAUGE + 5, seed_rhs=SEED_RHS + 5)
     if name == "shamir_24x24x24x48_ns16_12pt":
         ns = 16
         return dict(dims=(24, 24, 24, 48), ns=ns, m0=1.8, mq=0.005,
