@@ -275,17 +275,22 @@ hipError_t launch_dwf(const Geom& g0, const F& in, const LF& links, const Real* 
     Geom g = g0;
     if constexpr (!HOP) g.nsb = 0;
     int T = round_up(g.G * g.Ns, 64);
-    // Ns = 16 with a recurrence-form M5 / M5^T: applied in registers, no LDS buffer
+    // Ns = 16 or 8 with a recurrence-form M5 / M5^T: applied in registers, no LDS buffer
     constexpr bool STRUCT = MIXM == MIX_SA || MIXM == MIX_AS;
-    const bool reg = STRUCT && g.Ns == 16;
+    const bool reg = STRUCT && (g.Ns == 16 || g.Ns == 8);
     size_t sm = kernel_smem<Real>(g.G, g.Ns, HOP, MIXM != MIX_NONE && !reg);
     const int rpb = o.rpb > 0 && o.rpb < o.nrhs ? o.rpb : o.nrhs;
     o.rpb = rpb;
     const unsigned ng = o.ngroups > 0 ? (unsigned)o.ngroups : (unsigned)((o.nrhs + rpb - 1) / rpb);
     const dim3 grid((unsigned)g.nblocks * ng), block(T);
-    if (g.Ns <= 8)
+    if (g.Ns <= 8) {
+        if constexpr (STRUCT)
+            if (reg)
+                return launch_kernel(k_dwf<Real, F, LF, 8, HOP, MIXM, true, Pro, Epi>, grid, block, sm, st, g, in,
+                                     links, table, pro, epi, o);
         return launch_kernel(k_dwf<Real, F, LF, 8, HOP, MIXM, false, Pro, Epi>, grid, block, sm, st, g, in, links,
                              table, pro, epi, o);
+    }
     if (g.Ns <= 16) {
         if constexpr (STRUCT)
             if (reg)

@@ -774,15 +774,19 @@ __device__ __forceinline__ void mix_structured(Real* base, const Real* __restric
 }
 
 // ---------------------------------------------------------------------------
-// M5 and M5^T in registers for Ns = 16.  The 16 slices of a 4D site sit in one
-// 16-lane row of the wavefront (lane = s), so the recurrences above run across
-// lanes with DPP row moves instead of an LDS transpose:
+// M5 and M5^T in registers for Ns = 16 and Ns = 8.  The N slices of a 4D site
+// sit in N consecutive lanes of one 16-lane row of the wavefront (lane = s;
+// at N = 8 a row holds two sites), so the recurrences above run across lanes
+// with DPP row moves instead of an LDS transpose:
 //   - the sweep al_k = F_k x_k - G_k al_{k-1} is a linear recurrence, done as
-//     a Hillis-Steele scan (shifts by 1, 2, 4, 8 within the row, multiplied by
-//     the products of the -G_j they skip);
+//     a Hillis-Steele scan (shifts by 1, 2, 4 [, 8] within the row,
+//     multiplied by the products of the -G_j they skip, which are zero where
+//     a shift would reach past the site's first slice);
 //   - the corner equation needs al_{N-1} and the first input in every lane
-//     (row broadcasts);
-//   - Y and Y^T are one cyclic neighbour each (row rotation).
+//     (row broadcasts; at N = 8, where a row holds two sites, a lane read
+//     through the LDS crossbar);
+//   - Y and Y^T are one cyclic neighbour each (row rotation; lane read at
+//     N = 8).
 // The recurrence runs with s reversed for one chirality (REV): the shifts
 // then go the other way along the row.
 // ---------------------------------------------------------------------------
@@ -808,36 +812,72 @@ __device__ __forceinline__ double mov(double x) {
 }
 }  // namespace dpp
 
-// value at recurrence index k - D (0 if k < D)
+// value at recurrence index k - D (0 if k < D; at N = 8 the other site's
+// value where k < D, which the scan multiplies by zero)
 template <bool REV, int D, class Real>
 __device__ __forceinline__ Real rshift(Real x) {
     return dpp::mov<REV ? dpp::shl(D) : dpp::shr(D)>(x);
 }
-// value at recurrence index (k - 1) mod 16
-template <bool REV, class Real>
-__device__ __forceinline__ Real rprev(Real x) {
-    return dpp::mov<REV ? dpp::ror(15) : dpp::ror(1)>(x);
+// x of lane src (byte address src * 4) through the LDS crossbar, no memory
+__device__ __forceinline__ float lane_read(float x, int addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
 }
-// value at recurrence index K (0 or 15) of the lane's row
-template <bool REV, int K, class Real>
-__device__ __forceinline__ Real ridx(Real x) {
-    return dpp::mov<dpp::bcast(REV ? 15 - K : K)>(x);
+__device__ __forceinline__ double lane_read(double x, int addr) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Lanes a slice reads at N = 8 (byte addresses for lane_read): the slice of
+// recurrence index k - 1 mod 8, and those of indices 0 and 7 of its site.
+// (Two sites share a DPP row there, so a row move cannot serve both; one
+// value per lane also keeps the compiler from carrying both sites' copies.)
+struct Lanes8 {
+    int prev, first, last;
+};
+template <bool REV>
+__device__ __forceinline__ Lanes8 lanes8(int s) {
+    const int base = (int)__lane_id() & ~7;
+    const int sprev = REV ? (s + 1) & 7 : (s + 7) & 7;
+    return Lanes8{(base + sprev) * 4, (base + (REV ? 7 : 0)) * 4, (base + (REV ? 0 : 7)) * 4};
+}
+
+// value at recurrence index (k - 1) mod N
+template <bool REV, int N, class Real>
+__device__ __forceinline__ Real rprev(Real x, const Lanes8& l8) {
+    if constexpr (N == 16)
+        return dpp::mov<REV ? dpp::ror(15) : dpp::ror(1)>(x);
+    else
+        return lane_read(x, l8.prev);
+}
+// value at recurrence index K (0 or N - 1) of the lane's site
+template <bool REV, int N, int K, class Real>
+__device__ __forceinline__ Real ridx(Real x, const Lanes8& l8) {
+    if constexpr (N == 16)
+        return dpp::mov<dpp::bcast(REV ? 15 - K : K)>(x);
+    else
+        return lane_read(x, K == 0 ? l8.first : l8.last);
 }
 
 // One chirality block (12 components) of M5 (MODE = MIX_SA) or M5^T / M5^T g5
-// (MIX_AS) on the lane's slice s, coefficients C = [F G B P Q O][16] of that
+// (MIX_AS) on the lane's slice s, coefficients C = [F G B P Q O][N] of that
 // block in recurrence order.  Every lane of the row must execute it.
-template <class Real, int MODE, bool REV>
-__device__ __forceinline__ void mix_reg16(Real* v, const Real* __restrict__ C, int s) {
-    const int k = REV ? 15 - s : s;
-    const Real F = C[k], G = C[16 + k], B = C[32 + k], P = C[48 + k], Q = C[64 + k], O = C[80 + k];
-    const Real F0 = C[0], G0 = C[16];
+template <class Real, int MODE, bool REV, int N>
+__device__ __forceinline__ void mix_regn(Real* v, const Real* __restrict__ C, int s) {
+    static_assert(N == 8 || N == 16, "register fifth-dimension matrices need 8 or 16 slices");
+    const int k = REV ? N - 1 - s : s;
+    Lanes8 l8{};
+    if constexpr (N == 8) l8 = lanes8<REV>(s);
+    const Real F = C[k], G = C[N + k], B = C[2 * N + k], P = C[3 * N + k], Q = C[4 * N + k], O = C[5 * N + k];
+    const Real F0 = C[0], G0 = C[N];
     const Real Fk = k ? F : (Real)0;  // the sweep starts at k = 1
     // scan multipliers: A_d(k) = prod_{j = k-d+1..k} (-G_j), zero where k < d
     const Real A1 = k ? -G : (Real)0;
     const Real A2 = A1 * rshift<REV, 1>(A1);
     const Real A4 = A2 * rshift<REV, 2>(A2);
-    const Real A8 = A4 * rshift<REV, 4>(A4);
+    Real A8 = 0;
+    if constexpr (N == 16) A8 = A4 * rshift<REV, 4>(A4);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         const Real h = v[c];
@@ -845,16 +885,16 @@ __device__ __forceinline__ void mix_reg16(Real* v, const Real* __restrict__ C, i
         if constexpr (MODE == MIX_SA)
             x = h;
         else
-            x = P * h + Q * rprev<REV>(h);  // Y^T sqrt(w)^-1 h
+            x = P * h + Q * rprev<REV, N>(h, l8);  // Y^T sqrt(w)^-1 h
         Real al = Fk * x;
         al += A1 * rshift<REV, 1>(al);
         al += A2 * rshift<REV, 2>(al);
         al += A4 * rshift<REV, 4>(al);
-        al += A8 * rshift<REV, 8>(al);
-        const Real w0 = F0 * ridx<REV, 0>(x) + G0 * ridx<REV, 15>(al);
+        if constexpr (N == 16) al += A8 * rshift<REV, 8>(al);
+        const Real w0 = F0 * ridx<REV, N, 0>(x, l8) + G0 * ridx<REV, N, N - 1>(al, l8);
         if constexpr (MODE == MIX_SA) {
             const Real w = al + B * w0;
-            v[c] = P * w + Q * rprev<REV>(w);  // sqrt(w)^-1 Y w
+            v[c] = P * w + Q * rprev<REV, N>(w, l8);  // sqrt(w)^-1 Y w
         } else {
             v[c] = O * al + B * w0;  // sign sqrt(w) X^-T (...)
         }
@@ -880,13 +920,14 @@ __device__ __forceinline__ void mix_reg16(Real* v, const Real* __restrict__ C, i
 // ---------------------------------------------------------------------------
 
 // A prologue or epilogue with set_ns(n) sets the component-block stride of
-// its fields (kernels at Ns = 16 make it a compile-time constant).
+// its fields (kernels with the fifth-dimension matrices in registers make it a
+// compile-time constant).
 template <class T>
-__device__ __forceinline__ auto set_ns16(T& t, int) -> decltype(t.set_ns(16L)) {
-    t.set_ns(16L);
+__device__ __forceinline__ auto set_ns_const(T& t, long n, int) -> decltype(t.set_ns(16L)) {
+    t.set_ns(n);
 }
 template <class T>
-__device__ __forceinline__ void set_ns16(T&, long) {}
+__device__ __forceinline__ void set_ns_const(T&, long, long) {}
 
 // An epilogue with a second output: kPost = true, a member ptab (the offset
 // of the M5^T gamma_5 coefficients from the kernel's table, indexed per
@@ -941,16 +982,17 @@ __device__ __forceinline__ void mix_lds(Real* v, Real* hb, const Real* __restric
     }
 }
 
-// M5 (MIX_SA) or M5^T (MIX_AS) in registers at Ns = 16; every lane of the
-// workgroup calls it (rows of inactive sites are whole rows)
-template <class Real, int MODE>
+// M5 (MIX_SA) or M5^T (MIX_AS) in registers at Ns = N (8 or 16); every lane
+// of the workgroup calls it (rows of inactive sites are whole rows, or at
+// N = 8 half rows whose lanes hold zeros)
+template <class Real, int MODE, int N>
 __device__ __forceinline__ void mix_reg(Real* v, const Real* __restrict__ tb, int s) {
     // the coefficient loads stay after what precedes, whose register peak
     // they would otherwise raise
     __builtin_amdgcn_sched_barrier(0);
     constexpr bool rev0 = MODE == MIX_AS, rev1 = MODE != MIX_AS;  // M5: L_- reversed; M5^T: L_+^T
-    mix_reg16<Real, MODE, rev0>(v, tb, s);
-    mix_reg16<Real, MODE, rev1>(v + 12, tb + 6 * 16, s);
+    mix_regn<Real, MODE, rev0, N>(v, tb, s);
+    mix_regn<Real, MODE, rev1, N>(v + 12, tb + 6 * N, s);
 }
 
 struct KOpt {
@@ -999,26 +1041,26 @@ template <class F, class E> struct HopPipe {
 template <class Real, class F, class LF, int NSMAX, bool HOP, int MIXM, bool REGMIX, class Pro, class Epi>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(std::is_same<F, FS>::value ? 4 : 1)))
 k_dwf(Geom g, F in0, LF links, const Real* __restrict__ table, Pro pro0, Epi epi0, KOpt o) {
-    // REGMIX: Ns == 16, M5 / M5^T applied in registers (no LDS transpose)
+    // REGMIX: Ns == NSMAX (16 or 8), M5 / M5^T applied in registers (no LDS transpose)
     constexpr bool MIX = MIXM != MIX_NONE && !REGMIX;
-    // At Ns = 16 the slices of a component block lie 16 vectors apart in
-    // every field; with that stride a constant, the vector loads and stores
-    // of a site share one address (immediate offsets) and the index
-    // arithmetic folds.
+    // With the fifth-dimension matrices in registers Ns = NSMAX: the slices of
+    // a component block lie NSMAX vectors apart in every field, and with that
+    // stride a constant, the vector loads and stores of a site share one
+    // address (immediate offsets) and the index arithmetic folds.
     F in = in0;
     Pro pro = pro0;
     Epi epi = epi0;
     if constexpr (REGMIX) {
-        in.ns = 16;
-        set_ns16(pro, 0);
-        set_ns16(epi, 0);
+        in.ns = NSMAX;
+        set_ns_const(pro, NSMAX, 0);
+        set_ns_const(epi, NSMAX, 0);
     }
     // phase 4 runs in the same way as phase 2 (registers or LDS)
     constexpr bool POST = EpiPost<Epi>::value;
     static_assert(!POST || MIXM == MIX_SA || MIXM == MIX_AS, "phase 4 needs a kernel with a structured phase 2");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int LS = LdsLink<Real>::STR;
-    const int Ns = REGMIX ? 16 : g.Ns;
+    const int Ns = REGMIX ? NSMAX : g.Ns;
     const int tid = threadIdx.x, T = blockDim.x;
 
     // workgroup -> (group of right-hand sides, lattice block)
@@ -1094,13 +1136,13 @@ k_dwf(Geom g, F in0, LF links, const Real* __restrict__ table, Pro pro0, Epi epi
         }
         if constexpr (MIX)
             mix_lds<Real, NSMAX, MIXM>(v, hb, table + rhs * o.table_rstride, Ns, nsites, sl, s, act, hs, tid, T);
-        if constexpr (REGMIX) mix_reg<Real, MIXM>(v, table + rhs * o.table_rstride, s);
+        if constexpr (REGMIX) mix_reg<Real, MIXM, NSMAX>(v, table + rhs * o.table_rstride, s);
         double part = 0;
         if (act) part = epi(rhs, i5, s, v);
         if constexpr (POST) {
             const Real* tb = table + epi.ptab + rhs * o.table_rstride;
             if constexpr (REGMIX) {
-                mix_reg<Real, MIX_AS>(v, tb, s);
+                mix_reg<Real, MIX_AS, NSMAX>(v, tb, s);
             } else {
                 __syncthreads();  // every lane has read back its phase-2 vector
                 mix_lds<Real, NSMAX, MIX_AS>(v, hb, tb, Ns, nsites, sl, s, act, hs, tid, T);

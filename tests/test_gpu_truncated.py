@@ -5,8 +5,8 @@ cycle runs k plain CG iterations from zero with p = r, Algorithm 1) returns
 the reconstruction of its k-th iterate (Eq. (10)).  The oracle's solve capped
 at k iterations returns the same quantity in FP64, so the two differ only by
 the rounding of the low-precision inner kernels T, A, B, C, D (with the
-fifth-dimension recurrences in registers at Ns = 16 and through LDS at
-Ns = 1, 2, 5, 12, 32, the 12-real or 18-real links, the fused CG updates and the
+fifth-dimension recurrences in registers at Ns = 8 and 16 and through LDS
+at Ns = 1, 2, 5, 12, 32, the 12-real or 18-real links, the fused CG updates and the
 two reductions): unlike a converged solve, whose FP64 defect
 correction would absorb an error of the inner operator, this comparison sees
 it directly.  (The oracle's truncated iterates are pinned to the Krylov
@@ -44,6 +44,9 @@ PROBS = {
                             0.5, 65, 66),
     "ns32": lambda: Problem((4, 4, 2, 8), 32, 1.8, 0.05, *(2 * [_rng.uniform(0.5, 1.5, 32)]), 0.5, 67, 68,
                             antiperiodic=True),
+    # Ns = 8: two sites per DPP row, the recurrences in registers
+    "ns8": lambda: Problem((4, 6, 2, 8), 8, 1.8, 0.05, _rng.uniform(0.2, 1.4, 8), _rng.uniform(0.5, 1.5, 8),
+                           0.5, 73, 74, antiperiodic=True),
     # the degenerate fifth dimensions: one slice (M5 is a number per
     # chirality) and two
     "ns1": lambda: Problem((4, 4, 2, 4), 1, 1.2, 0.3, [0.7], [1.3], 0.5, 69, 70),
