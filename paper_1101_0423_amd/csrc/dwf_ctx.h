@@ -275,9 +275,9 @@ hipError_t launch_dwf(const Geom& g0, const F& in, const LF& links, const Real* 
     Geom g = g0;
     if constexpr (!HOP) g.nsb = 0;
     int T = round_up(g.G * g.Ns, 64);
-    // Ns = 16 or 8 with a recurrence-form M5 / M5^T: applied in registers, no LDS buffer
+    // Ns = 8, 16 or 32 with a recurrence-form M5 / M5^T: applied in registers, no LDS buffer
     constexpr bool STRUCT = MIXM == MIX_SA || MIXM == MIX_AS;
-    const bool reg = STRUCT && (g.Ns == 16 || g.Ns == 8);
+    const bool reg = STRUCT && (g.Ns == 8 || g.Ns == 16 || g.Ns == 32);
     size_t sm = kernel_smem<Real>(g.G, g.Ns, HOP, MIXM != MIX_NONE && !reg);
     const int rpb = o.rpb > 0 && o.rpb < o.nrhs ? o.rpb : o.nrhs;
     o.rpb = rpb;
@@ -299,6 +299,10 @@ hipError_t launch_dwf(const Geom& g0, const F& in, const LF& links, const Real* 
         return launch_kernel(k_dwf<Real, F, LF, 16, HOP, MIXM, false, Pro, Epi>, grid, block, sm, st, g, in, links,
                              table, pro, epi, o);
     }
+    if constexpr (STRUCT)
+        if (reg)
+            return launch_kernel(k_dwf<Real, F, LF, 32, HOP, MIXM, true, Pro, Epi>, grid, block, sm, st, g, in,
+                                 links, table, pro, epi, o);
     return launch_kernel(k_dwf<Real, F, LF, 32, HOP, MIXM, false, Pro, Epi>, grid, block, sm, st, g, in, links,
                          table, pro, epi, o);
 }

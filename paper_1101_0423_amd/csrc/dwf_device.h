@@ -774,14 +774,17 @@ __device__ __forceinline__ void mix_structured(Real* base, const Real* __restric
 }
 
 // ---------------------------------------------------------------------------
-// M5 and M5^T in registers for Ns = 16 and Ns = 8.  The N slices of a 4D site
-// sit in N consecutive lanes of one 16-lane row of the wavefront (lane = s;
-// at N = 8 a row holds two sites), so the recurrences above run across lanes
-// with DPP row moves instead of an LDS transpose:
+// M5 and M5^T in registers for Ns = 8, 16 and 32.  The N slices of a 4D site
+// sit in N consecutive lanes of the wavefront (lane = s; a 16-lane DPP row
+// holds two sites at N = 8, a site spans two rows at N = 32), so the
+// recurrences above run across lanes with DPP row moves instead of an LDS
+// transpose:
 //   - the sweep al_k = F_k x_k - G_k al_{k-1} is a linear recurrence, done as
 //     a Hillis-Steele scan (shifts by 1, 2, 4 [, 8] within the row,
 //     multiplied by the products of the -G_j they skip, which are zero where
-//     a shift would reach past the site's first slice);
+//     a shift would reach past the site's first slice or the row); at N = 32
+//     the second row then takes the first row's last value times its own
+//     prefix product of the -G_j;
 //   - the corner equation needs al_{N-1} and the first input in every lane
 //     (row broadcasts; at N = 8, where a row holds two sites, a lane read
 //     through the LDS crossbar);
@@ -829,35 +832,52 @@ __device__ __forceinline__ double lane_read(double x, int addr) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Lanes a slice reads at N = 8 (byte addresses for lane_read): the slice of
-// recurrence index k - 1 mod 8, and those of indices 0 and 7 of its site.
-// (Two sites share a DPP row there, so a row move cannot serve both; one
-// value per lane also keeps the compiler from carrying both sites' copies.)
-struct Lanes8 {
-    int prev, first, last;
+// Lanes a slice reads at N = 8 and 32 (byte addresses for lane_read): the
+// slice of recurrence index k - 1 mod N, those of indices 0 and N - 1 of its
+// site and, at N = 32, that of index 15 (the end of the first DPP row in
+// recurrence order).  (At N = 8 two sites share a DPP row, at N = 32 a site
+// spans two, so row moves cannot serve these; one value per lane also keeps
+// the compiler from carrying several copies across the component loop.)
+struct LaneAddr {
+    int prev, first, last, carry;
 };
-template <bool REV>
-__device__ __forceinline__ Lanes8 lanes8(int s) {
-    const int base = (int)__lane_id() & ~7;
-    const int sprev = REV ? (s + 1) & 7 : (s + 7) & 7;
-    return Lanes8{(base + sprev) * 4, (base + (REV ? 7 : 0)) * 4, (base + (REV ? 0 : 7)) * 4};
+template <bool REV, int N>
+__device__ __forceinline__ LaneAddr lane_addrs(int s) {
+    const int base = (int)__lane_id() & ~(N - 1);
+    const int sprev = REV ? (s + 1) & (N - 1) : (s + N - 1) & (N - 1);
+    return LaneAddr{(base + sprev) * 4, (base + (REV ? N - 1 : 0)) * 4, (base + (REV ? 0 : N - 1)) * 4,
+                    (base + (REV ? N - 16 : 15)) * 4};
 }
 
 // value at recurrence index (k - 1) mod N
 template <bool REV, int N, class Real>
-__device__ __forceinline__ Real rprev(Real x, const Lanes8& l8) {
+__device__ __forceinline__ Real rprev(Real x, const LaneAddr& la) {
     if constexpr (N == 16)
         return dpp::mov<REV ? dpp::ror(15) : dpp::ror(1)>(x);
     else
-        return lane_read(x, l8.prev);
+        return lane_read(x, la.prev);
 }
 // value at recurrence index K (0 or N - 1) of the lane's site
 template <bool REV, int N, int K, class Real>
-__device__ __forceinline__ Real ridx(Real x, const Lanes8& l8) {
+__device__ __forceinline__ Real ridx(Real x, const LaneAddr& la) {
     if constexpr (N == 16)
         return dpp::mov<dpp::bcast(REV ? 15 - K : K)>(x);
     else
-        return lane_read(x, K == 0 ? l8.first : l8.last);
+        return lane_read(x, K == 0 ? la.first : la.last);
+}
+// value at recurrence index k - D within the DPP row, 1 where that leaves the row
+template <bool REV, int D>
+__device__ __forceinline__ float rshift_or1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(1.0f), __float_as_int(x),
+                                                      REV ? dpp::shl(D) : dpp::shr(D), 0xF, 0xF, false));
+}
+template <bool REV, int D>
+__device__ __forceinline__ double rshift_or1(double x) {
+    const long long b = __double_as_longlong(x), one = __double_as_longlong(1.0);
+    constexpr int ctrl = REV ? dpp::shl(D) : dpp::shr(D);
+    const int lo = __builtin_amdgcn_update_dpp((int)one, (int)b, ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(one >> 32), (int)(b >> 32), ctrl, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // One chirality block (12 components) of M5 (MODE = MIX_SA) or M5^T / M5^T g5
@@ -865,19 +885,33 @@ __device__ __forceinline__ Real ridx(Real x, const Lanes8& l8) {
 // block in recurrence order.  Every lane of the row must execute it.
 template <class Real, int MODE, bool REV, int N>
 __device__ __forceinline__ void mix_regn(Real* v, const Real* __restrict__ C, int s) {
-    static_assert(N == 8 || N == 16, "register fifth-dimension matrices need 8 or 16 slices");
+    static_assert(N == 8 || N == 16 || N == 32, "register fifth-dimension matrices need 8, 16 or 32 slices");
     const int k = REV ? N - 1 - s : s;
-    Lanes8 l8{};
-    if constexpr (N == 8) l8 = lanes8<REV>(s);
+    LaneAddr la{};
+    if constexpr (N != 16) la = lane_addrs<REV, N>(s);
     const Real F = C[k], G = C[N + k], B = C[2 * N + k], P = C[3 * N + k], Q = C[4 * N + k], O = C[5 * N + k];
     const Real F0 = C[0], G0 = C[N];
     const Real Fk = k ? F : (Real)0;  // the sweep starts at k = 1
     // scan multipliers: A_d(k) = prod_{j = k-d+1..k} (-G_j), zero where k < d
+    // (and, at N = 32, where the product would reach into the other DPP row)
     const Real A1 = k ? -G : (Real)0;
     const Real A2 = A1 * rshift<REV, 1>(A1);
     const Real A4 = A2 * rshift<REV, 2>(A2);
     Real A8 = 0;
-    if constexpr (N == 16) A8 = A4 * rshift<REV, 4>(A4);
+    if constexpr (N >= 16) A8 = A4 * rshift<REV, 4>(A4);
+    // N = 32: the scan runs in each DPP row alone; the second row (indices
+    // 16..31) then adds prod_{j=16..k} (-G_j) times al_15, the product being
+    // the row's prefix product of A1 (a multiplicative scan that reads 1
+    // beyond the row start)
+    Real Pc = 0;
+    if constexpr (N == 32) {
+        Real pr = A1;
+        pr *= rshift_or1<REV, 1>(pr);
+        pr *= rshift_or1<REV, 2>(pr);
+        pr *= rshift_or1<REV, 4>(pr);
+        pr *= rshift_or1<REV, 8>(pr);
+        Pc = k >= 16 ? pr : (Real)0;
+    }
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         const Real h = v[c];
@@ -885,16 +919,17 @@ __device__ __forceinline__ void mix_regn(Real* v, const Real* __restrict__ C, in
         if constexpr (MODE == MIX_SA)
             x = h;
         else
-            x = P * h + Q * rprev<REV, N>(h, l8);  // Y^T sqrt(w)^-1 h
+            x = P * h + Q * rprev<REV, N>(h, la);  // Y^T sqrt(w)^-1 h
         Real al = Fk * x;
         al += A1 * rshift<REV, 1>(al);
         al += A2 * rshift<REV, 2>(al);
         al += A4 * rshift<REV, 4>(al);
-        if constexpr (N == 16) al += A8 * rshift<REV, 8>(al);
-        const Real w0 = F0 * ridx<REV, N, 0>(x, l8) + G0 * ridx<REV, N, N - 1>(al, l8);
+        if constexpr (N >= 16) al += A8 * rshift<REV, 8>(al);
+        if constexpr (N == 32) al += Pc * lane_read(al, la.carry);
+        const Real w0 = F0 * ridx<REV, N, 0>(x, la) + G0 * ridx<REV, N, N - 1>(al, la);
         if constexpr (MODE == MIX_SA) {
             const Real w = al + B * w0;
-            v[c] = P * w + Q * rprev<REV, N>(w, l8);  // sqrt(w)^-1 Y w
+            v[c] = P * w + Q * rprev<REV, N>(w, la);  // sqrt(w)^-1 Y w
         } else {
             v[c] = O * al + B * w0;  // sign sqrt(w) X^-T (...)
         }
