@@ -173,16 +173,16 @@ def summarize_rocpd(path):
         full = [d for d in v if d >= 0.5 * max(v)]
         print(f"{k[:40]:40s} {len(v):8d} {sum(v) / 1e6:10.2f} {statistics.mean(v) / 1e3:9.2f} {len(full):6d} "
               f"{statistics.median(full) / 1e3:10.2f} {100 * sum(v) / tot:5.1f}%")
-    # inner iterations inside the solves: A B finish C D finish, followed by A
-    pat = ["hop_eo_m5t", "hop_oe_g5_dir", "finish_reduction", "hop_eo_m5", "hop_oe_m5_cgupd_m5t",
-           "finish_reduction"]
-    its = [i for i in range(len(trace) - 6)
-           if [trace[i + j][0] for j in range(7)] == pat + ["hop_eo_m5t"]]
+    # inner iterations inside the solves: A B C D finish, followed by A
+    pat = ["hop_eo_m5t", "hop_oe_g5_dir", "hop_eo_m5", "hop_oe_m5_cgupd_m5t", "finish_reduction"]
+    n = len(pat)
+    its = [i for i in range(len(trace) - n)
+           if [trace[i + j][0] for j in range(n + 1)] == pat + ["hop_eo_m5t"]]
     if its:
         longest = max(trace[i][2] - trace[i][1] for i in its)
         its = [i for i in its if trace[i][2] - trace[i][1] >= 0.5 * longest]
-        per = statistics.median(trace[i + 6][1] - trace[i][1] for i in its)
-        busy = statistics.median(sum(trace[i + j][2] - trace[i + j][1] for j in range(6)) for i in its)
+        per = statistics.median(trace[i + n][1] - trace[i][1] for i in its)
+        busy = statistics.median(sum(trace[i + j][2] - trace[i + j][1] for j in range(n)) for i in its)
         print(f"\ninner iterations inside the solves ({len(its)} with every kernel live): median period "
               f"{per / 1e3:.2f} us start to start, kernels busy {busy / 1e3:.2f} us of it")
         for j, k in enumerate(pat):

@@ -308,7 +308,8 @@ hipError_t launch_dwf(const Geom& g0, const F& in, const LF& links, const Real* 
 }
 
 // finish kernel modes
-enum FinMode { FIN_AUX = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_OUTER = 3 };
+// (alpha is finished by kernel C's first workgroups, EpiStoreAlpha)
+enum FinMode { FIN_AUX = 0, FIN_BETA = 2, FIN_OUTER = 3 };
 
 // mask (per right-hand side, NULL = all) restricts FIN_AUX and FIN_OUTER
 hipError_t launch_finish(const double* partials, int nblocks, int nrhs, CgState st, int mode, hipStream_t s,

@@ -976,6 +976,17 @@ template <class E>
 struct EpiPost<E, std::void_t<decltype(E::kPost)>> {
     static constexpr bool value = E::kPost;
 };
+// An epilogue with kPre = true also does one-workgroup work per right-hand
+// side before the stencil: pre(rhs) for the launch's j-th right-hand side in
+// workgroup j (mod the grid size).
+template <class E, class = void>
+struct EpiPre {
+    static constexpr bool value = false;
+};
+template <class E>
+struct EpiPre<E, std::void_t<decltype(E::kPre)>> {
+    static constexpr bool value = E::kPre;
+};
 
 // The fifth-dimension matrix through LDS: each lane writes its (site, s)
 // vector, the workgroup mixes the columns (chirality, site, real component),
@@ -1107,6 +1118,9 @@ k_dwf(Geom g, F in0, LF links, const Real* __restrict__ table, Pro pro0, Epi epi
     const int j0 = grp * rpb, j1 = min(nsel, j0 + rpb);
     auto rhs_of = [&](int j) { return o.glist ? o.glist[1 + j] : j; };
 
+    if constexpr (EpiPre<Epi>::value)
+        for (int j = blockIdx.x; j < nsel; j += gridDim.x) epi.pre(rhs_of(j));
+
     if (o.live) {  // uniform early exit when no right-hand side of the group is live
         int any = 0;
         for (int j = j0; j < j1; ++j) any |= o.live[rhs_of(j)];
@@ -1212,6 +1226,7 @@ struct CgState {
                         // right-hand side stops, so the host sees it without a copy
 };
 
+
 // ---------------------------------------------------------------------------
 // prologues (phase 1 without a hop)
 // ---------------------------------------------------------------------------
@@ -1270,6 +1285,50 @@ struct EpiStore {
         return RED ? norm2_24(v) : 0.0;
     }
 };
+
+// Kernel C's epilogue: stores like EpiStore, and its first workgroups finish
+// the reduction of kernel B for one right-hand side each before the stencil:
+// (p, C C^dag p) = |u|^2 from B's block sums and alpha = |r|^2 / that, or a
+// breakdown when it is not positive.  Kernel C does not read alpha, and the
+// kernel boundary makes it visible to kernel D.  The first wave sums the
+// block sums in a fixed order (lane l takes l, l + 64, ...; then a fixed
+// butterfly), so alpha does not depend on the launch's shape or its other
+// right-hand sides.
+template <class F>
+struct EpiStoreAlpha {
+    static constexpr bool kReduce = false;
+    static constexpr bool kPre = true;
+    F out;
+    const double* partials;  // [nrhs][nparts] block sums of kernel B
+    int nparts;
+    const CgState* st;       // the CG state (a copy in device memory)
+    __device__ __forceinline__ void set_ns(long n) { out.ns = n; }
+    template <class Real>
+    __device__ __forceinline__ double operator()(int rhs, long i, int s, Real* v) const {
+        out.store(rhs, i, s, v);  // the next kernel gathers it: cached
+        return 0.0;
+    }
+    __device__ __forceinline__ void pre(int r) const;
+};
+
+template <class F>
+__device__ __forceinline__ void EpiStoreAlpha<F>::pre(int r) const {
+    if (threadIdx.x >= 64) return;
+    if (!st->live[r]) return;
+    const double* pr = partials + (long)r * nparts;
+    double a = 0;
+    for (int i = threadIdx.x; i < nparts; i += 64) a += pr[i];
+    const double tot = wave_sum(a);
+    if (threadIdx.x != 0) return;
+    st->uu[r] = tot;
+    if (!(tot > 0.0) || !isfinite(tot)) {  // breakdown
+        st->status[r] = 2;
+        st->live[r] = 0;
+        if (st->live_host) st->live_host[r] = 0;
+    } else {
+        st->alpha[r] = st->rr[r] / tot;
+    }
+}
 
 // stores nothing; returns |v|^2
 struct EpiNorm {

@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kFinT) k_finish(const double* __restrict__ par
                                                   int mode, const int* __restrict__ mask) {
     __shared__ double red[kFinT / 64];
     const int r = blockIdx.x;
-    if ((mode == FIN_ALPHA || mode == FIN_BETA) && !st.live[r]) return;
+    if (mode == FIN_BETA && !st.live[r]) return;
     if ((mode == FIN_AUX || mode == FIN_OUTER) && mask && !mask[r]) return;
     const double* __restrict__ pr = partials + (long)r * nblocks;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
@@ -198,15 +198,6 @@ __global__ void __launch_bounds__(kFinT) k_finish(const double* __restrict__ par
     } else if (mode == FIN_OUTER) {
         st.aux[r] = tot;
         st.rr[r] = tot;
-    } else if (mode == FIN_ALPHA) {
-        st.uu[r] = tot;
-        if (!(tot > 0.0) || !isfinite(tot)) {
-            st.status[r] = 2;
-            st.live[r] = 0;
-            if (st.live_host) st.live_host[r] = 0;
-        } else {
-            st.alpha[r] = st.rr[r] / tot;
-        }
     } else if (mode == FIN_BETA) {
         if (!isfinite(tot)) {
             st.status[r] = 2;

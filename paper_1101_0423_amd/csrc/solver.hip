@@ -9,14 +9,14 @@
 // direction p is kept across restarts), with the automatic switch to defect
 // correction when reliable updates stall (Sec. 2.3).
 //
-// One inner CG iteration is four fused stencil kernels plus two one-block
-// reduction finishers (Secs. 3.2-3.5).  The search direction is carried as
+// One inner CG iteration is four fused stencil kernels plus one one-block
+// reduction finisher (Secs. 3.2-3.5).  The search direction is carried as
 // u = C^dag p: C^dag is linear, so u follows p's recurrence p = r + beta p as
 // u = C^dag r + beta u, and p itself is never formed (it is only for the
 // solution update, which takes y += alpha u):
 //   A: t2 = M5^T D^EO t1                                            (even)
-//   B: u  = r - g5 D^OE t2 + beta u,  |u|^2 = (p, C C^dag p)        (odd) -> alpha
-//   C: t3 = M5 D^EO u                                               (even)
+//   B: u  = r - g5 D^OE t2 + beta u,  |u|^2 = (p, C C^dag p)        (odd)
+//   C: t3 = M5 D^EO u; its first workgroups finish B's |u|^2 -> alpha (even)
 //   D: q  = u - M5 D^OE t3;  y += alpha u;  r -= alpha q;  |r|^2;
 //      t1 = M5^T g5 r for the next iteration                       (odd) -> beta
 // (C^dag r = r - g5 D^OE M5^T D^EO M5^T g5 r.)
@@ -221,6 +221,10 @@ class Engine : public EngineBase {
         DWF_HIP(hipHostMalloc(&live_pin, (size_t)K * sizeof(int), hipHostMallocMapped));
         memset(live_pin, 0, (size_t)K * sizeof(int));
         DWF_HIP(hipHostGetDevicePointer((void**)&w.st.live_host, live_pin, 0));
+        // a copy of the state's pointers in device memory, for kernel C's alpha
+        if ((rc = st_dev.alloc(sizeof(CgState)))) return rc;
+        DWF_HIP(hipMemcpyAsync(st_dev.p, &w.st, sizeof(CgState), hipMemcpyHostToDevice, s));
+        DWF_HIP(hipStreamSynchronize(s));
         DWF_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
         DWF_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
         TS = (long)tables_size(c->Ns);
@@ -464,7 +468,7 @@ class Engine : public EngineBase {
     LinkD18 lk64[2];
     std::vector<SlotCtl> sl;
     Workspace w;
-    DevBuf tabs64, tabs32, aux;
+    DevBuf tabs64, tabs32, aux, st_dev;
     long TS = 0;
     int nbmax = 0;
     int* dmask[NMASK] = {};
@@ -683,9 +687,11 @@ class Engine : public EngineBase {
             glo(1), lo(L_T23), lk[1], nullptr, ProLoad<F>{lo(L_T23)},
             EpiCgB<F, F>{lo(L_R), lo(L_U), lo(L_P).ptrs(), w.st.beta, w.st.ecr, dmask[M_FORM]}, kopt_in(live, true), s);
     }
+    // C also finishes kernel B's reduction (alpha) in its first workgroups
     hipError_t kC(const int* live) {
-        return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiStore<F>>(
-            glo(0), lo(L_U), lk[0], slo(ST_M5), ProLoad<F>{lo(L_U)}, EpiStore<F>{lo(L_T23)}, kopt_in(live, false), s);
+        return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiStoreAlpha<F>>(
+            glo(0), lo(L_U), lk[0], slo(ST_M5), ProLoad<F>{lo(L_U)},
+            EpiStoreAlpha<F>{lo(L_T23), part(), glo(1).nblocks, st_dev.as<CgState>()}, kopt_in(live, false), s);
     }
     hipError_t kD(const int* live) {
         return launch_dwf<Real, F, LF, true, MIX_SA, ProLoad<F>, EpiCgD<F, F, FY>>(
@@ -700,7 +706,6 @@ class Engine : public EngineBase {
         if (cur_ng1 && (e = kE(live, LIST_F1, cur_ng1)) != hipSuccess) return e;
         if ((e = kA(live)) != hipSuccess) return e;
         if ((e = kB(live)) != hipSuccess) return e;
-        if ((e = fin(glo(1).nblocks, FIN_ALPHA)) != hipSuccess) return e;
         if ((e = kC(live)) != hipSuccess) return e;
         if ((e = kD(live)) != hipSuccess) return e;
         return fin(glo(1).nblocks, FIN_BETA);
