@@ -44,20 +44,23 @@ constexpr int kMaxBatch = 8;
 constexpr int kReplayCap = 16;
 // lanes of at least this many half 5D sites (16^3 x 32 x 8) fill the GPU alone
 constexpr long kLargeV5h = 1L << 19;
-// large lanes that may run at once (DWF_SERVE_LARGE_LANES overrides).  On the
-// served stream of four fields (200 requests at 0.8 of the plain capacity, and
-// 60 at once), 1 serialises too much (p99 9.9 s, fewer solves/s than a FIFO
-// of plain solves), no limit lets large solves share the GPU so long that p99
-// exceeds the FIFO's (8.7 s vs 8.3 s), and 2-3 beat the FIFO on p50, p99 and
-// solves/s alike
+// large requests in service at once, admitted in arrival order, and so large
+// lanes that run at once (DWF_SERVE_LARGE_LANES overrides).  On the served
+// stream of four fields (200 requests at 0.8 of the plain capacity, and 60 at
+// once): 1 leaves the GPU part idle under the smaller "large" solves (fewer
+// solves/s than a FIFO of plain solves, p99 9.1-9.2 s against 6.9 s); 2 beats
+// the FIFO on p50, p99 and solves/s in every run (p99 5.7-6.1 s); 3 by less
+// (p99 6.4 s); without the arrival order, lanes batched their newer requests
+// ahead of older ones in other lanes and p99 varied from 6.4 to 8.8 s
 int large_lanes() {
     static const int n = [] {
         const char* e = getenv("DWF_SERVE_LARGE_LANES");
-        const int v = e ? atoi(e) : 3;
+        const int v = e ? atoi(e) : 2;
         return v > 0 ? v : 1;
     }();
     return n;
 }
+int large_requests() { return large_lanes(); }
 
 struct Request {
     uint64_t ticket = 0;
@@ -169,6 +172,25 @@ bool large_turn(const Server& S, const Lane* L) {
         if (oldest_request(o, &t) && (t < mine || (t == mine && o < L))) ++older;
     }
     return older < large_lanes();
+}
+
+// Whether a large lane may admit request q: fewer than large_requests()
+// requests of large lanes (in service or queued) arrived before it (lock
+// held).  Large requests thus enter service in arrival order, a few at a
+// time: one such solve fills the GPU, so running more of them at once only
+// stretches each (batching them gains nothing), and letting a lane batch its
+// newer requests would serve them ahead of older ones in other lanes.
+bool large_admissible(const Server& S, const Request& q) {
+    int older = 0;
+    for (auto& kv : S.lanes) {
+        const Lane* o = kv.second.get();
+        if (!o->large || o->cancel || o->closing || o->exited) continue;
+        for (auto& r : o->slot)
+            if (r && r->ticket < q.ticket) ++older;
+        for (auto& r : o->queue)
+            if (r->ticket < q.ticket) ++older;
+    }
+    return older < large_requests();
 }
 
 // Join and drop the lanes whose thread has ended (lock held).  The lane of
@@ -294,6 +316,7 @@ void lane_main(Lane* L) {
             if (leave || L->cancel) break;
             for (int r = 0; r < L->K && !L->queue.empty(); ++r) {
                 if (L->slot[r]) continue;
+                if (L->large && !large_admissible(S, *L->queue.front())) break;  // queue: arrival order
                 adm.emplace_back(r, L->queue.front());
                 L->queue.pop_front();
             }
