@@ -142,55 +142,38 @@ void service_end(Server& S) {
 
 void lane_main(Lane* L);
 
-// Submission time of the oldest request a lane holds (in a slot or queued);
-// false if it holds none (lock held).
-bool oldest_request(const Lane* L, Clock::time_point* t) {
-    bool any = false;
-    for (auto& q : L->slot)
-        if (q && (!any || q->t_submit < *t)) {
-            *t = q->t_submit;
-            any = true;
-        }
-    for (auto& q : L->queue)
-        if (!any || q->t_submit < *t) {
-            *t = q->t_submit;
-            any = true;
-        }
-    return any;
-}
-
-// A large lane's turn: its oldest request is among the large_lanes() oldest
-// of the large lanes that hold requests (lock held).
-bool large_turn(const Server& S, const Lane* L) {
-    Clock::time_point mine;
-    if (!oldest_request(L, &mine)) return true;
-    int older = 0;
-    for (auto& kv : S.lanes) {
-        const Lane* o = kv.second.get();
-        if (o == L || !o->large || o->cancel || o->closing || o->exited) continue;
-        Clock::time_point t;
-        if (oldest_request(o, &t) && (t < mine || (t == mine && o < L))) ++older;
-    }
-    return older < large_lanes();
-}
-
-// Whether a large lane may admit request q: fewer than large_requests()
-// requests of large lanes (in service or queued) arrived before it (lock
-// held).  Large requests thus enter service in arrival order, a few at a
-// time: one such solve fills the GPU, so running more of them at once only
-// stretches each (batching them gains nothing), and letting a lane batch its
-// newer requests would serve them ahead of older ones in other lanes.
-bool large_admissible(const Server& S, const Request& q) {
+// Requests of large lanes (in service or queued) that arrived before ticket t
+// (lock held).
+int older_large(const Server& S, uint64_t t) {
     int older = 0;
     for (auto& kv : S.lanes) {
         const Lane* o = kv.second.get();
         if (!o->large || o->cancel || o->closing || o->exited) continue;
         for (auto& r : o->slot)
-            if (r && r->ticket < q.ticket) ++older;
+            if (r && r->ticket < t) ++older;
         for (auto& r : o->queue)
-            if (r->ticket < q.ticket) ++older;
+            if (r->ticket < t) ++older;
     }
-    return older < large_requests();
+    return older;
+}
+
+// Whether a large lane may admit request q: fewer than large_requests()
+// requests of large lanes arrived before it (lock held).  Large requests thus
+// enter service in arrival order, a few at a time: one such solve nearly
+// fills the GPU, so running more of them at once only stretches each
+// (batching them gains nothing), and letting a lane batch its newer requests
+// would serve them ahead of older ones in other lanes.
+bool large_admissible(const Server& S, const Request& q) { return older_large(S, q.ticket) < large_requests(); }
+
+// A large lane's turn: its oldest request (in a slot or queued) is
+// admissible, so that a lane whose requests all wait for older ones sleeps
+// instead of spinning (lock held).
+bool large_turn(const Server& S, const Lane* L) {
+    const Request* oldest = nullptr;
+    for (auto& q : L->slot)
+        if (q && (!oldest || q->ticket < oldest->ticket)) oldest = q.get();
+    if (!L->queue.empty() && (!oldest || L->queue.front()->ticket < oldest->ticket)) oldest = L->queue.front().get();
+    return !oldest || large_admissible(S, *oldest);
 }
 
 // Join and drop the lanes whose thread has ended (lock held).  The lane of
