@@ -304,8 +304,11 @@ int dwf_propagator_dev(dwf_ctx *ctx, const double *eta_dev, double *out_dev, int
  * dwf_submit -- enqueue one solve request on the context's device server
  * (continuous batching: requests on the same gauge field and fifth-dimension
  * weights are solved together in the multi-RHS kernels, with their own mq;
- * admission is limited by the HBM budget of dwf_opts).  b (host, one spinor)
- * is copied before the call returns.  *ticket identifies the request.
+ * admission is limited by the HBM budget of dwf_opts).  Requests on lattices
+ * of at least 2^19 half 5D sites, where one solve nearly fills the GPU, enter
+ * service in arrival order, two at a time (environment variable
+ * DWF_SERVE_LARGE_LANES), beside the smaller ones.  b (host, one spinor) is
+ * copied before the call returns.  *ticket identifies the request.
  */
 int dwf_submit(dwf_ctx *ctx, const double *b, const dwf_solve_params *params, uint64_t *ticket);
 
