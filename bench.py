@@ -32,6 +32,9 @@ WORKLOADS = {  # name, inner precision, link_compress (-1: the library's default
     "fp16": ("odwf_16x16x16x32_ns16_fp16", 2, -1),
     "fp64": ("odwf_16x16x16x32_ns16", 0, 0),
 }
+# every choice above runs on this lattice; the counter-traffic summaries in
+# profiles/ are named after it and the --prec choice
+LATTICE = "odwf_16x16x16x32_ns16"
 KERNEL_SOURCES = ["paper_1101_0423_amd/csrc/dwf_device.h", "paper_1101_0423_amd/csrc/solver.hip"]
 
 
@@ -604,7 +607,7 @@ def main():
     r = run_solve(dwf, ctx, bd, xd, prec, lc, args.steps, args.warmup, args.kernel_launches, say)
     g = golden_samples("odwf_16x16x16x32_ns16")
     fwd = sampled_forward_error(xd, g) if g is not None else None
-    traffic = counter_traffic(r["dominant"], wname, args.prec)
+    traffic = counter_traffic(r["dominant"], LATTICE, args.prec)
     roofline = dict(r["roofline"], traffic=traffic)
     line = dict(metric=METRIC, value=r["gflops"], unit="Gflops", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=r["ms_per_step"], higher_is_better=True,
@@ -628,7 +631,9 @@ def main():
             steps=max(3, args.steps // 4), gflops=r16["gflops"], hbm_gbs=r16["hbm_gbs"],
             ms_per_step=r16["ms_per_step"], iters=r16["iters"], true_residual=r16["true_residual"],
             forward_error=sampled_forward_error(xd, g) if g is not None else None, converged=r16["converged"],
-            dominant_kernel=dict(r16["roofline"], kernel=r16["dominant"]), kernels=r16["kernels"])
+            dominant_kernel=dict(r16["roofline"], kernel=r16["dominant"],
+                                 traffic=counter_traffic(r16["dominant"], LATTICE, "fp16")),
+            kernels=r16["kernels"])
     ctx.close()
     del bd, xd
     torch.cuda.empty_cache()
