@@ -195,10 +195,12 @@ void dwf_default_params(dwf_solve_params *params);
  *   gauge  : host pointer, FP64, layout above (copied to the device).
  *   dims   : Lx, Ly, Lz, Lt, each even and >= 2.
  *   Ns     : 1 <= Ns <= 32.   m0 in (0, 2).   mq: quark mass (kappa = mq / (2 m0)).
+ *            At most 2^30 5D half-lattice sites: Lx Ly Lz Lt / 2 * Ns <= 2^30.
  *   sigma, omega : host arrays of Ns doubles, omega_s > 0.
  *   opts   : NULL for defaults.
- * Errors: DWF_EINVAL for bad sizes or parameters, or when (1 + cL) or X of
- * Eq. (7) is singular; DWF_ENOMEM; DWF_EDEVICE.
+ * Errors: DWF_EINVAL for bad sizes or parameters (checked before the gauge
+ * field is read), or when (1 + cL) or X of Eq. (7) is singular; DWF_ENOMEM;
+ * DWF_EDEVICE.
  */
 int dwf_create(dwf_ctx **out, const double *gauge, const int dims[4], int Ns,
                double m0, double mq, const double *sigma, const double *omega,

@@ -70,6 +70,23 @@ def test_create_rejects_bad_arguments(kw, msg):
     assert msg in err
 
 
+@pytest.mark.parametrize("dims,ns", [((128, 128, 128, 66), 16), ((128, 128, 128, 128), 32)])
+def test_create_rejects_a_lattice_beyond_the_index_range(dims, ns):
+    # the 5D half-lattice may hold at most 2^30 sites (V4 / 2 * Ns; 128^3 x 64
+    # at Ns = 16 is exactly the limit); larger ones are refused before the
+    # gauge field is read, so a short buffer stands in for it
+    import paper_1101_0423_amd as dwf
+    L = dwf.lib()
+    h = ctypes.c_void_p()
+    dp = ctypes.POINTER(ctypes.c_double)
+    g, sigma, omega = np.zeros(16), np.zeros(ns), np.ones(ns)
+    rc = L.dwf_create(ctypes.byref(h), g.ctypes.data_as(dp), (ctypes.c_int * 4)(*dims), ns, 1.8, 0.1,
+                      sigma.ctypes.data_as(dp), omega.ctypes.data_as(dp), None)
+    assert int(np.prod(dims)) // 2 * ns > 2 ** 30
+    assert rc == dwf.DWF_EINVAL and h.value is None
+    assert "too large" in L.dwf_last_error().decode()
+
+
 def test_x_singular_rejected():
     """X = a + b L_+ with Ns = 1: a - kappa b = 0 makes X singular (Eq. (7))."""
     import paper_1101_0423_amd as dwf
