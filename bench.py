@@ -110,11 +110,40 @@ def cpu_baseline(w, U, b, n1=2, n2=12, reps=3):
     v5h = lx * ly * lz * lt * w["ns"] // 2
     flops = v5h * (5280.0 + 192.0 * w["ns"] + 288.0)
     work = sum(sum(v) for v in t.values())
+    # one hop (D_w^OE) and one application of C (Eq. (11)) on the same field,
+    # median of 5 each: 1320 flops per 5D site per hop, C = two hops, two
+    # dense M5 and the subtraction
+    th, tc = [], []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        oracle.hop(U, w["dims"], w["ns"], 1, b)
+        th.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        oracle.schur_c(*args, b)
+        tc.append(time.perf_counter() - t0)
+    hop_s, c_s = float(np.median(th)), float(np.median(tc))
+    # the whole FP64 solve of the small case (4^4, Ns = 8 Shamir), median of 3
+    import dwf_inputs as inp
+    w0 = inp.workload("shamir_4x4x4x4_ns8")
+    U0 = inp.gauge_field(w0["dims"], w0["eps"], seed=w0["seed_gauge"])
+    b0 = inp.gaussian_spinor(w0["dims"], w0["ns"], seed=w0["seed_rhs"])
+    ts, info = [], None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, info = oracle.solve(U0, w0["dims"], w0["ns"], w0["m0"], w0["mq"], w0["sigma"], w0["omega"], b0,
+                               tol=1e-10)
+        ts.append(time.perf_counter() - t0)
+    work += sum(th) + sum(tc) + sum(ts)
     return dict(value=round(flops / per_it * 1e-9, 3), unit="Gflops", cores=oracle.num_threads(), kind="oracle",
                 sample=f"FP64 CPU oracle on the same 16^3x32x16 solve: median of {reps} runs capped at {n1} and "
-                       f"at {n2} CG iterations, per-iteration time from their difference ({work:.1f} s of CPU "
-                       f"work), converted with the same flop convention",
-                seconds_per_iteration=per_it)
+                       f"at {n2} CG iterations, per-iteration time from their difference, converted with the "
+                       f"same flop convention; also one hop and one C (median of 5) and the whole 4^4 x 8 solve "
+                       f"(median of 3); {work:.1f} s of CPU work in all",
+                seconds_per_iteration=per_it,
+                hop=dict(seconds=hop_s, gflops=round(1320.0 * v5h / hop_s * 1e-9, 3)),
+                schur_c=dict(seconds=c_s, gflops=round((2640.0 + 96.0 * w["ns"] + 24.0) * v5h / c_s * 1e-9, 3)),
+                small_solve=dict(workload="shamir_4x4x4x4_ns8", tol=1e-10, seconds=float(np.median(ts)),
+                                 iters=info["iters"], converged=info["converged"]))
 
 
 # the inner kernels of dwf_time_kernels (T once per cycle, then one iteration A B C D)
