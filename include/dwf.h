@@ -51,13 +51,13 @@ extern "C" {
 
 /* status codes */
 #define DWF_OK 0
-#define DWF_PENDING 1
-#define DWF_EINVAL (-1)
-#define DWF_ENOMEM (-2)
-#define DWF_EDEVICE (-3)
-#define DWF_ENOCONV (-4)
-#define DWF_EBUSY (-5)
-#define DWF_ENOTFOUND (-6)
+#define DWF_PENDING 1        /* dwf_poll: the request is not finished */
+#define DWF_EINVAL (-1)      /* bad argument, size or parameter */
+#define DWF_ENOMEM (-2)      /* device or host allocation failed */
+#define DWF_EDEVICE (-3)     /* a HIP call failed */
+#define DWF_ENOCONV (-4)     /* a solve stopped before its tolerance (x holds the best iterate) */
+#define DWF_EBUSY (-5)       /* reserved: no call returns it (calls on one context serialise) */
+#define DWF_ENOTFOUND (-6)   /* dwf_poll: unknown or already collected ticket */
 
 /* operators for dwf_apply (all in the host spinor layout, full 5D lattice) */
 #define DWF_OP_DW 0      /* D_w on every slice, Eq. (2)                                */
