@@ -7,6 +7,7 @@ solution that dwf_solve finds for that request alone.  The per-slot arithmetic
 does not depend on the other slots, so the two agree to the last bit; the test
 allows 1e-12 (relative).
 """
+import ctypes
 import time
 
 import numpy as np
@@ -105,16 +106,31 @@ def test_mixed_masses_each_equals_alone():
 
 
 def test_served_solution_matches_oracle():
+    # also the ownership rules of the served form: dwf_submit copies b (the
+    # caller's array is overwritten right after it returns), and dwf_poll
+    # leaves x untouched while the request is pending
     import paper_1101_0423_amd as dwf
     mq = 0.05
     b = rhs(SMALL, 50)
+    b_submitted = b.copy()
     c = SMALL.context()
     try:
         t = c.submit(b, mq=mq)
-        rc, x, st = wait(t, c.spinor_shape())
+        b[...] = rhs(SMALL, 51)
+        xs = np.full(c.spinor_shape(), 7.0)
+        st0 = dwf.SolveStats()
+        rc = dwf.lib().dwf_poll(ctypes.c_uint64(t), xs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                ctypes.byref(st0), 0)
+        print(f"[serve] first poll: {'pending' if rc == dwf.DWF_PENDING else 'final'}", flush=True)
+        if rc == dwf.DWF_PENDING:
+            assert np.all(xs == 7.0)
+            rc, x, st = wait(t, c.spinor_shape())
+        else:  # already done: that poll collected it
+            x = xs
     finally:
         c.close()
     assert rc == dwf.DWF_OK
+    b = b_submitted
     xo, info = oracle.solve(SMALL.U, SMALL.dims, SMALL.ns, SMALL.m0, mq, SMALL.sigma, SMALL.omega, b, tol=1e-12)
     assert info["converged"]
     err = rel(x, xo)
