@@ -403,14 +403,20 @@ def stream_copy(src, dst, nontemporal=False, stream=None):
     """Plain device copy src -> dst (torch tensors of equal byte size, a
     multiple of 16) with cached or non-temporal accesses (dwf_stream_copy):
     the calibration reference of the memory counters.  stream: a HIP stream
-    handle other than the legacy null stream (default: torch's current one)."""
+    handle other than the legacy null stream (default: torch's current
+    stream, which then must not be torch's default one, the null stream).
+    Work that wrote src on other streams must be finished first."""
     nb = src.numel() * src.element_size()
     if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
         raise ValueError("contiguous device tensors expected")
     if dst.numel() * dst.element_size() != nb or nb % 16:
         raise ValueError("equal sizes, a multiple of 16 bytes, expected")
+    sp = _stream_ptr(stream)
+    if not sp.value:
+        raise ValueError("stream_copy needs a stream other than the legacy null stream, "
+                         "e.g. torch.cuda.Stream().cuda_stream")
     _check(lib().dwf_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nb,
-                                 int(bool(nontemporal)), src.device.index, _stream_ptr(stream)))
+                                 int(bool(nontemporal)), src.device.index, sp))
 
 
 def odwf_weights(ns, lambda_min, lambda_max):

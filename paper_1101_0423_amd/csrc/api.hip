@@ -589,9 +589,9 @@ int dwf_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, int nontem
     if (!src_dev || !dst_dev) return fail(DWF_EINVAL, "NULL buffer");
     if (bytes % 16) return fail(DWF_EINVAL, "bytes must be a multiple of 16");
     if (nontemporal != 0 && nontemporal != 1) return fail(DWF_EINVAL, "nontemporal must be 0 or 1");
-    DWF_HIP(hipSetDevice(device));
     hipStream_t s = (hipStream_t)stream;
     if (!s) return fail(DWF_EINVAL, "a stream is required");
+    DWF_HIP(hipSetDevice(device));
     DWF_HIP(stream_copy(src_dev, dst_dev, bytes, nontemporal != 0, s));
     DWF_HIP(hipStreamSynchronize(s));
     return DWF_OK;

@@ -87,6 +87,26 @@ def test_create_rejects_a_lattice_beyond_the_index_range(dims, ns):
     assert "too large" in L.dwf_last_error().decode()
 
 
+def test_stream_copy_and_time_kernels_reject_bad_arguments():
+    # checked before any HIP call, so small dummy addresses stand in for the
+    # device buffers and the stream
+    import paper_1101_0423_amd as dwf
+    L = dwf.lib()
+    a, b, s = ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(1024)
+    assert L.dwf_stream_copy(None, b, 16, 0, 0, s) == dwf.DWF_EINVAL
+    assert L.dwf_stream_copy(a, None, 16, 0, 0, s) == dwf.DWF_EINVAL
+    assert L.dwf_stream_copy(a, b, 24, 0, 0, s) == dwf.DWF_EINVAL
+    assert "multiple of 16" in L.dwf_last_error().decode()
+    assert L.dwf_stream_copy(a, b, 16, 2, 0, s) == dwf.DWF_EINVAL
+    assert L.dwf_stream_copy(a, b, 16, 0, 0, None) == dwf.DWF_EINVAL
+    assert "stream" in L.dwf_last_error().decode()
+    ms, by = np.zeros(5), np.zeros(5)
+    dp = ctypes.POINTER(ctypes.c_double)
+    p = dwf.default_params()
+    assert L.dwf_time_kernels(None, ctypes.byref(p), 1, 1, ms.ctypes.data_as(dp), by.ctypes.data_as(dp)) \
+        == dwf.DWF_EINVAL
+
+
 def test_x_singular_rejected():
     """X = a + b L_+ with Ns = 1: a - kappa b = 0 makes X singular (Eq. (7))."""
     import paper_1101_0423_amd as dwf
