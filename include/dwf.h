@@ -101,7 +101,7 @@ typedef struct dwf_opts {
     int antiperiodic_t;      /* 0: periodic in t (default); 1: antiperiodic               */
     int device;              /* HIP device ordinal (default 0)                            */
     int sites_per_block;     /* 4D sites per workgroup in the stencil; 0 = automatic      */
-    int xcd_remap;           /* 0/1: place consecutive lattice blocks on one XCD (default 1);
+    int xcd_remap;           /* 0 (default) or 1: consecutive lattice blocks on one XCD;
                                 -1: hardware dispatch order                               */
     size_t hbm_budget_bytes; /* serving admission budget; 0 = 80% of free device memory   */
 } dwf_opts;

@@ -137,6 +137,28 @@ def test_iteration_cap_reports_noconv(small_ctx):
     assert abs(res - st[0]["true_residual"]) <= 1e-8 * res
 
 
+@pytest.mark.parametrize("opt", ["xcd_remap=-1", "sites_per_block=8", "check_every=1", "use_graph=0"])
+def test_launch_options_keep_the_solution(opt):
+    # options that change only how the work is launched (hardware dispatch
+    # order instead of the XCD mapping, 8 sites per workgroup, a host check
+    # after every iteration, plain launches instead of graphs): the solve
+    # still meets both bars against the oracle
+    import paper_1101_0423_amd as dwf
+    key, val = opt.split("=")
+    ckw = {key: int(val)} if key in ("xcd_remap", "sites_per_block") else {}
+    skw = {key: int(val)} if key in ("check_every", "use_graph") else {}
+    c = SMALL.context(**ckw)
+    try:
+        x, st, rc = c.solve(SMALL.b, inner_prec=1, **skw)
+    finally:
+        c.close()
+    print(f"[solve] {opt}: iters={st[0]['iters']} G={st[0]['sites_per_block']}", flush=True)
+    assert rc == dwf.DWF_OK
+    check(SMALL, x, oracle_solution(SMALL, "small"))
+    if key == "sites_per_block":
+        assert st[0]["sites_per_block"] == 8
+
+
 def test_initial_guess_resumes(small_ctx):
     import paper_1101_0423_amd as dwf
     xo = oracle_solution(SMALL, "small")
