@@ -159,6 +159,33 @@ def test_launch_options_keep_the_solution(opt):
         assert st[0]["sites_per_block"] == 8
 
 
+def test_caller_stream_gives_identical_results():
+    # the device-pointer forms on a stream of the caller's instead of the
+    # context's own: the same kernels in the same order, every reduction in a
+    # fixed order, so bit-identical solutions and operator outputs
+    import torch
+
+    import paper_1101_0423_amd as dwf
+    c = SMALL.context()
+    try:
+        b = torch.from_numpy(SMALL.b).cuda()
+        x0, x1 = torch.zeros_like(b), torch.zeros_like(b)
+        y0, y1 = torch.zeros_like(b), torch.zeros_like(b)
+        st0, rc0 = c.solve_dev(b, x0, inner_prec=1)
+        c.apply_dev(dwf.OP_D, b, y0, prec=dwf.PREC_FP64)
+        torch.cuda.synchronize()
+        side = torch.cuda.Stream()
+        st1, rc1 = c.solve_dev(b, x1, inner_prec=1, stream=side.cuda_stream)
+        c.apply_dev(dwf.OP_D, b, y1, prec=dwf.PREC_FP64, stream=side.cuda_stream)
+        torch.cuda.synchronize()
+    finally:
+        c.close()
+    assert rc0 == rc1 == dwf.DWF_OK
+    assert st0[0]["iters"] == st1[0]["iters"]
+    assert torch.equal(x0, x1) and torch.equal(y0, y1)
+    check(SMALL, x1.cpu().numpy(), oracle_solution(SMALL, "small"))
+
+
 def test_initial_guess_resumes(small_ctx):
     import paper_1101_0423_amd as dwf
     xo = oracle_solution(SMALL, "small")
