@@ -217,14 +217,22 @@ def _golden(name):
                          ids=["fp32-12real", "fp32-18real", "fp16-12real"])
 def test_full_size_solve(name, prec, lc):
     """The primary workload (16^3x32, Ns = 16) in the launch configuration of
-    the benchmark: true residual with the oracle's operator over the whole
-    lattice, forward error on the oracle's stored samples."""
+    the benchmark (dwf_solve_dev on device-resident b and x): true residual
+    with the oracle's operator over the whole lattice, forward error on the
+    oracle's stored samples."""
+    import torch
+
     import paper_1101_0423_amd as dwf
     print(f"[solve] full size {name} prec={prec}", flush=True)
     P = Problem.workload(name)
     c = P.context()
     try:
-        x, st, rc = c.solve(P.b, inner_prec=prec, link_compress=lc)
+        bd = torch.from_numpy(P.b).cuda()
+        xd = torch.zeros_like(bd)
+        st, rc = c.solve_dev(bd, xd, inner_prec=prec, link_compress=lc)
+        torch.cuda.synchronize()
+        x = xd.cpu().numpy()
+        del bd, xd
         print("stats", st[0], flush=True)
         assert rc == dwf.DWF_OK, st
         check(P, x)
